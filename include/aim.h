@@ -1,0 +1,260 @@
+/*
+ * aim.h - C ABI of the MI355X adaptive-integral-method (AIM) library.
+ *
+ * The library solves time-harmonic scattering from perfectly conducting
+ * (PEC) surfaces with the EFIE method of moments on RWG basis functions,
+ * accelerated by AIM: the paper (Wei & Yilmaz, "A Hybrid Parallelization of
+ * AIM for Multi-Core Clusters", Sections 2.1-2.2) benchmarks PEC plates and
+ * spheres meshed with triangles at ~lambda/9, lit by an x-polarised plane
+ * wave travelling toward -z, and measures the bistatic RCS sigma_theta_theta
+ * against a reference through err_theta_theta (its eq. 1). Each iteration of
+ * its diagonally preconditioned iterative solve applies the AIM product:
+ * projection onto a regular grid, an FFT propagation step on the doubled
+ * (zero-padded) grid, interpolation back, and the near-zone correction
+ * (Section 4.1 and its footnote on pruning the zero-padded FFTs).
+ *
+ * Conventions for every entry point:
+ *  - Every call returns aim_status; no C++ exception crosses the ABI. On a
+ *    non-OK status aim_last_error() returns a message for the calling thread.
+ *  - "device" pointers are HIP device allocations on the current device (for
+ *    example torch tensors); "host" pointers are ordinary process memory.
+ *  - Complex numbers are interleaved (re, im): c64 = 2 x float, c128 =
+ *    2 x double. Multi-RHS vectors are column-major [sum_N][nrhs] with
+ *    leading dimension sum_N (each right-hand side contiguous).
+ *  - hip_stream is a hipStream_t (NULL = the null stream). Calls that say
+ *    "asynchronous" only enqueue work on it; the others synchronise it.
+ *  - A plan is not thread-safe; distinct plans are independent.
+ *  - Units: SI (metres, hertz, square metres); angles in radians.
+ *  - Time convention exp(+j w t); G(R) = exp(-j k R) / (4 pi R).
+ */
+#ifndef AIM_H
+#define AIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AIM_OK = 0,
+  AIM_ERR_ARG = -1,    /* invalid argument (NULL pointer, size, parameter) */
+  AIM_ERR_MESH = -2,   /* invalid mesh: index out of range, degenerate
+                          triangle, edge shared by more than two triangles */
+  AIM_ERR_HIP = -3,    /* a HIP runtime call or kernel launch failed */
+  AIM_ERR_NOMEM = -4,  /* the allocator returned NULL */
+  AIM_ERR_NOCONV = -5, /* GMRES reached max_iter before the tolerance */
+  AIM_ERR_STATE = -6   /* call not valid for this plan (e.g. FP32 data absent) */
+} aim_status;
+
+/* Arithmetic of the AIM product.
+ * AIM_FP64:  projection, FFTs, Green's-function multiply, interpolation and
+ *            near correction in complex double.
+ * AIM_MIXED: the same steps in complex float (operator data rounded from the
+ *            FP64 set-up); the solver keeps FP64 Krylov vectors and an FP64
+ *            outer residual (iterative refinement). */
+typedef enum { AIM_FP64 = 0, AIM_MIXED = 1 } aim_precision;
+
+/* A PEC triangle surface (paper Section 2.1). Host memory, copied by
+ * aim_setup/aim_host_plan; the caller may free it afterwards.
+ * verts: nv x 3 doubles (metres); tris: nt x 3 int32 vertex indices (0-based;
+ * closed surfaces consistently oriented). freq_hz > 0. */
+typedef struct {
+  int64_t nv;
+  const double *verts;
+  int64_t nt;
+  const int32_t *tris;
+  double freq_hz;
+} aim_mesh;
+
+/* AIM parameters (paper Section 2.2 sets the moment-matching order and the
+ * near-zone size gamma; grid spacing is chosen empirically there).
+ * h_lambda            grid spacing in wavelengths (> 0), e.g. 0.1
+ * order               stencil order M >= 1: (M+1)^3 nodes, moments matched
+ *                     up to order M in each coordinate, e.g. 2
+ * near_radius_lambda  near zone: basis pairs whose centres are within this
+ *                     distance (wavelengths, >= 0), e.g. 0.3 (= 3 h)
+ * fft_min_pad         0: FFT length per dimension = smallest supported
+ *                     length >= 2 N_d - 1; otherwise a lower bound on it
+ * flags               AIM_FLAG_* below */
+typedef struct {
+  double h_lambda;
+  int32_t order;
+  int32_t fft_min_pad;
+  double near_radius_lambda;
+  int32_t flags;
+  int32_t reserved;
+} aim_params;
+
+#define AIM_FLAG_NO_MIXED 1 /* keep only FP64 operator data (AIM_MIXED -> AIM_ERR_STATE) */
+
+/* Device memory provider. alloc returns device memory of >= bytes (NULL on
+ * failure), ordered on `stream`; free releases it. Passing NULL for the
+ * allocator uses hipMalloc/hipFree. The allocator must outlive the plan. */
+typedef struct {
+  void *ctx;
+  void *(*alloc)(void *ctx, size_t bytes, void *stream);
+  void (*free)(void *ctx, void *p, void *stream);
+} aim_allocator;
+
+/* Plane wave arriving from direction r_hat(theta, phi), i.e. travelling along
+ * -r_hat, unit amplitude, polarised along theta_hat (pol 0) or phi_hat
+ * (pol 1) at (theta, phi). The paper's x-polarised wave toward -z is
+ * {0, 0, 0}. */
+typedef struct {
+  double theta;
+  double phi;
+  int32_t pol;
+  int32_t reserved;
+} aim_planewave;
+
+#define AIM_MAX_MESH 16
+
+/* Sizes of a plan (per mesh and totals). bytes_* are the algorithmic HBM
+ * bytes of one single-RHS product in each precision: operator data read once,
+ * vectors read/written once, grid traffic of the pruned pass structure. */
+typedef struct {
+  int32_t nmesh;
+  int32_t order;
+  int64_t n_total;                      /* sum of unknowns */
+  int64_t nnz_total;                    /* near-zone nonzeros */
+  int64_t n[AIM_MAX_MESH];              /* unknowns (interior edges) */
+  int64_t offset[AIM_MAX_MESH];         /* first row of each mesh */
+  int64_t nnz[AIM_MAX_MESH];
+  int32_t grid[AIM_MAX_MESH][3];        /* N_x, N_y, N_z */
+  int32_t pad[AIM_MAX_MESH][3];         /* FFT lengths P_x, P_y, P_z */
+  double h[AIM_MAX_MESH];               /* grid spacing, metres */
+  double x0[AIM_MAX_MESH][3];           /* coordinate of grid node 0 */
+  double k[AIM_MAX_MESH];               /* wavenumber, 1/m */
+  double bytes_fp64[AIM_MAX_MESH];
+  double bytes_mixed[AIM_MAX_MESH];
+  double device_bytes;                  /* device memory held by the plan */
+} aim_info;
+
+/* GMRES options. restart m (<= 200), relative-residual tolerance on
+ * ||b - A x|| / ||b|| (evaluated with the FP64 operator), iteration cap
+ * (inner iterations summed over restarts and refinement steps). */
+typedef struct {
+  double tol;
+  int32_t restart;
+  int32_t max_iter;
+  int32_t warm_start; /* 1: x_io holds the initial guess */
+  int32_t reserved;
+} aim_solve_opts;
+
+/* Per right-hand side results of aim_gmres_solve. */
+typedef struct {
+  int32_t iterations;      /* inner GMRES iterations */
+  int32_t converged;       /* 1 if the FP64 residual met tol */
+  int32_t matvec_low;      /* products in the requested precision */
+  int32_t matvec_fp64;     /* FP64 residual products */
+  double residual;         /* final ||b - A64 x|| / ||b|| */
+  double seconds;          /* wall time of the whole solve call */
+} aim_solve_stats;
+
+typedef struct aim_plan aim_plan;
+typedef struct aim_host_plan aim_host_plan;
+
+/* ---- set-up ------------------------------------------------------------ */
+
+/* Builds the operator for nmesh (1..AIM_MAX_MESH) scatterers: host planning
+ * (mesh validation, RWG table, grid, stencil anchors, near-zone pattern),
+ * then on the GPU the projection weights, the spectrum of the grid Green's
+ * function, and the FP64 near-zone matrix Z^MOM - Z^grid with singularity
+ * extraction on touching triangle pairs. Unknowns of mesh i occupy rows
+ * offset[i] .. offset[i]+n[i]-1. Synchronises hip_stream. On failure *out is
+ * NULL and nothing leaks. */
+aim_status aim_setup(const aim_mesh *meshes, int32_t nmesh, const aim_params *p,
+                     const aim_allocator *alloc, void *hip_stream, aim_plan **out);
+
+aim_status aim_plan_info(const aim_plan *plan, aim_info *out);
+
+/* Frees all device memory of the plan through its allocator. NULL-safe. */
+void aim_destroy(aim_plan *plan);
+
+/* ---- hot path ---------------------------------------------------------- */
+
+/* y = Z^AIM x for nrhs right-hand sides (asynchronous). x, y: device,
+ * column-major [n_total][nrhs]; c128 for AIM_FP64, c64 for AIM_MIXED.
+ * x and y must not overlap. */
+aim_status aim_matvec(aim_plan *plan, aim_precision prec, int32_t nrhs,
+                      const void *x, void *y, void *hip_stream);
+
+/* Solves Z^AIM x = b for nrhs_per_mesh plane waves on every mesh of the plan
+ * (waves: host, nrhs_per_mesh entries, the same set for every mesh) with
+ * restarted GMRES, right Jacobi preconditioning D = diag(Z^MOM), FP64
+ * (classical Gram-Schmidt, twice) Arnoldi and, for AIM_MIXED, an FP64 outer
+ * refinement loop r = b - A64 x around inner solves with the c64 operator.
+ * x_io: device c128 [n_total][nrhs_per_mesh]. stats: host
+ * [nrhs_per_mesh] (per wave, worst over meshes) or NULL. Synchronises.
+ * Returns AIM_ERR_NOCONV if some right-hand side missed tol (x_io then holds
+ * the last iterate). A zero right-hand side gives x = 0. */
+aim_status aim_gmres_solve(aim_plan *plan, aim_precision prec, int32_t nrhs_per_mesh,
+                           const aim_planewave *waves, const aim_solve_opts *opts,
+                           void *x_io, aim_solve_stats *stats, void *hip_stream);
+
+/* Plane-wave right-hand sides V_m = <f_m, E_inc> in FP64 (asynchronous).
+ * b: device c128 [n_total][nwaves]. */
+aim_status aim_excitation(aim_plan *plan, int32_t nwaves, const aim_planewave *waves,
+                          void *b, void *hip_stream);
+
+/* Bistatic sigma_theta_theta (m^2) of the currents x (device c128
+ * [n_total][nrhs]) on the grid theta[ntheta] x phi[nphi] (host, radians), in
+ * FP64: sigma = (k eta)^2 / (4 pi) |theta_hat . N|^2 with
+ * N = sum_n I_n int f_n exp(+j k r_hat . r') dS'. sigma_tt: host
+ * [nmesh][nrhs][ntheta][nphi]. Synchronises. */
+aim_status aim_rcs(aim_plan *plan, int32_t nrhs, const void *x, int32_t ntheta,
+                   const double *theta, int32_t nphi, const double *phi,
+                   double *sigma_tt, void *hip_stream);
+
+/* ---- host-only planning (no GPU needed) -------------------------------- */
+
+/* Runs only the host phase of aim_setup for one mesh: validation, RWG table,
+ * grid plan, anchors, near-zone CSR pattern. */
+aim_status aim_host_plan_build(const aim_mesh *mesh, const aim_params *p, aim_host_plan **out);
+
+/* Copies the host plan out (any pointer may be NULL to skip it).
+ * rwg:      [n][6] int32: edge vertex lo, hi, T+, T-, free vertex of T+, of T-
+ * anchors:  [n][3] int32 lowest stencil corner per dimension
+ * rowptr:   [n+1] int64, cols: [nnz] int32 (columns ascending per row)
+ * grid:     [3] int32 nodes, pad: [3] int32 FFT lengths, x0h: [4] double
+ *           (x0, y0, z0, h). */
+aim_status aim_host_plan_export(const aim_host_plan *hp, int64_t *n, int64_t *nnz,
+                                int32_t *rwg, int32_t *anchors, int64_t *rowptr,
+                                int32_t *cols, int32_t *grid, int32_t *pad, double *x0h);
+
+void aim_host_plan_destroy(aim_host_plan *hp);
+
+/* ---- inspection (tests) ------------------------------------------------ */
+
+/* Copies internal operator data of mesh `mesh` to host memory (synchronises):
+ *  AIM_DATA_LAMBDA64  [n][4][(M+1)^3] double  projection weights (q = x,y,z,div)
+ *  AIM_DATA_NEAR64    [nnz] c128              Z^near values (CSR order)
+ *  AIM_DATA_ZDIAG64   [n] c128                diag of Z^MOM
+ *  AIM_DATA_GHAT64    [Hx][Hy][Hz] c128       Green's spectrum octant,
+ *                     H_d = P_d/2 + 1, scaled by 1/(P_x P_y P_z)
+ * `bytes` must equal the size of the item. */
+#define AIM_DATA_LAMBDA64 1
+#define AIM_DATA_NEAR64 2
+#define AIM_DATA_ZDIAG64 3
+#define AIM_DATA_GHAT64 4
+aim_status aim_export(const aim_plan *plan, int32_t mesh, int32_t what, void *host_dst,
+                      size_t bytes);
+
+/* Runs only the far (grid) part of the product for one precision, stopping
+ * after `stage` (asynchronous): 1 = projection (grids [4 nrhs][Nx][Ny][Nz]),
+ * 2 = forward z pass, 3 = forward y pass, 4 = Green's multiply pass,
+ * 5 = inverse y pass, 6 = inverse z pass, and copies the resulting grid
+ * buffer (device, same precision as x) to `grid_out` (device, sized for the
+ * stage: [4 nrhs] x {NxNyNz, NxNyPz, NxPyPz, NxPyPz, NxNyPz, NxNyNz}). */
+aim_status aim_debug_far_stage(aim_plan *plan, aim_precision prec, int32_t mesh, int32_t nrhs,
+                               const void *x, int32_t stage, void *grid_out, void *hip_stream);
+
+const char *aim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AIM_H */

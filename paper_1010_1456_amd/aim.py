@@ -1,0 +1,365 @@
+"""Python binding of libaim.so (ctypes; argument marshalling only).
+
+Every step of the AIM product, the solve and the RCS runs in the library's
+HIP kernels; PyTorch only supplies device memory (its caching allocator, via
+the library's allocator callbacks) and streams. The names follow the C ABI in
+include/aim.h.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int32, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaim.so")
+
+AIM_OK = 0
+AIM_ERR_ARG = -1
+AIM_ERR_MESH = -2
+AIM_ERR_HIP = -3
+AIM_ERR_NOMEM = -4
+AIM_ERR_NOCONV = -5
+AIM_ERR_STATE = -6
+AIM_FP64 = 0
+AIM_MIXED = 1
+AIM_FLAG_NO_MIXED = 1
+AIM_MAX_MESH = 16
+AIM_DATA_LAMBDA64 = 1
+AIM_DATA_NEAR64 = 2
+AIM_DATA_ZDIAG64 = 3
+AIM_DATA_GHAT64 = 4
+
+EXPORTED = [
+    "aim_setup", "aim_plan_info", "aim_destroy", "aim_matvec", "aim_gmres_solve",
+    "aim_excitation", "aim_rcs", "aim_host_plan_build", "aim_host_plan_export",
+    "aim_host_plan_destroy", "aim_export", "aim_debug_far_stage", "aim_last_error",
+]
+
+
+class AimError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"aim status {status}: {msg}")
+        self.status = status
+
+
+class AimMesh(ctypes.Structure):
+    _fields_ = [("nv", c_int64), ("verts", POINTER(c_double)), ("nt", c_int64),
+                ("tris", POINTER(c_int32)), ("freq_hz", c_double)]
+
+
+class AimParams(ctypes.Structure):
+    _fields_ = [("h_lambda", c_double), ("order", c_int32), ("fft_min_pad", c_int32),
+                ("near_radius_lambda", c_double), ("flags", c_int32), ("reserved", c_int32)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_void_p, c_size_t, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p, c_void_p)
+
+
+class AimAllocator(ctypes.Structure):
+    _fields_ = [("ctx", c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN)]
+
+
+class AimPlanewave(ctypes.Structure):
+    _fields_ = [("theta", c_double), ("phi", c_double), ("pol", c_int32), ("reserved", c_int32)]
+
+
+class AimInfo(ctypes.Structure):
+    M = AIM_MAX_MESH
+    _fields_ = [("nmesh", c_int32), ("order", c_int32), ("n_total", c_int64),
+                ("nnz_total", c_int64), ("n", c_int64 * M), ("offset", c_int64 * M),
+                ("nnz", c_int64 * M), ("grid", (c_int32 * 3) * M), ("pad", (c_int32 * 3) * M),
+                ("h", c_double * M), ("x0", (c_double * 3) * M), ("k", c_double * M),
+                ("bytes_fp64", c_double * M), ("bytes_mixed", c_double * M),
+                ("device_bytes", c_double)]
+
+
+class AimSolveOpts(ctypes.Structure):
+    _fields_ = [("tol", c_double), ("restart", c_int32), ("max_iter", c_int32),
+                ("warm_start", c_int32), ("reserved", c_int32)]
+
+
+class AimSolveStats(ctypes.Structure):
+    _fields_ = [("iterations", c_int32), ("converged", c_int32), ("matvec_low", c_int32),
+                ("matvec_fp64", c_int32), ("residual", c_double), ("seconds", c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library. Raises if it has not been built: there is no
+    fallback implementation."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing; build it with `python -m paper_1010_1456_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = c_void_p
+    sig = {
+        "aim_setup": [POINTER(AimMesh), c_int32, POINTER(AimParams), POINTER(AimAllocator), P, POINTER(P)],
+        "aim_plan_info": [P, POINTER(AimInfo)],
+        "aim_matvec": [P, c_int32, c_int32, P, P, P],
+        "aim_gmres_solve": [P, c_int32, c_int32, POINTER(AimPlanewave), POINTER(AimSolveOpts), P,
+                            POINTER(AimSolveStats), P],
+        "aim_excitation": [P, c_int32, POINTER(AimPlanewave), P, P],
+        "aim_rcs": [P, c_int32, P, c_int32, POINTER(c_double), c_int32, POINTER(c_double),
+                    POINTER(c_double), P],
+        "aim_host_plan_build": [POINTER(AimMesh), POINTER(AimParams), POINTER(P)],
+        "aim_host_plan_export": [P, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32),
+                                 POINTER(c_int32), POINTER(c_int64), POINTER(c_int32),
+                                 POINTER(c_int32), POINTER(c_int32), POINTER(c_double)],
+        "aim_export": [P, c_int32, c_int32, P, c_size_t],
+        "aim_debug_far_stage": [P, c_int32, c_int32, c_int32, P, c_int32, P, P],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = c_int32
+    L.aim_destroy.argtypes = [P]
+    L.aim_destroy.restype = None
+    L.aim_host_plan_destroy.argtypes = [P]
+    L.aim_host_plan_destroy.restype = None
+    L.aim_last_error.argtypes = []
+    L.aim_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != AIM_OK:
+        raise AimError(status, lib().aim_last_error().decode())
+
+
+def _mesh_struct(verts, tris, freq_hz, keep):
+    v = np.ascontiguousarray(verts, dtype=np.float64)
+    t = np.ascontiguousarray(tris, dtype=np.int32)
+    keep.extend([v, t])
+    return AimMesh(v.shape[0], v.ctypes.data_as(POINTER(c_double)), t.shape[0],
+                   t.ctypes.data_as(POINTER(c_int32)), float(freq_hz))
+
+
+def _params(h_lambda, order, near_radius_lambda, fft_min_pad=0, flags=0):
+    return AimParams(float(h_lambda), int(order), int(fft_min_pad), float(near_radius_lambda),
+                     int(flags), 0)
+
+
+def _waves(waves):
+    arr = (AimPlanewave * len(waves))()
+    for i, w in enumerate(waves):
+        arr[i] = AimPlanewave(float(w[0]), float(w[1]), int(w[2]), 0)
+    return arr
+
+
+def host_plan(verts, tris, freq_hz, h_lambda=0.1, order=2, near_radius_lambda=0.3, fft_min_pad=0):
+    """Host phase only (no GPU): RWG table, anchors, near-zone CSR, grid."""
+    L = lib()
+    keep = []
+    m = _mesh_struct(verts, tris, freq_hz, keep)
+    p = _params(h_lambda, order, near_radius_lambda, fft_min_pad)
+    hp = c_void_p()
+    _check(L.aim_host_plan_build(ctypes.byref(m), ctypes.byref(p), ctypes.byref(hp)))
+    try:
+        n = c_int64()
+        nnz = c_int64()
+        _check(L.aim_host_plan_export(hp, ctypes.byref(n), ctypes.byref(nnz), None, None, None, None,
+                                      None, None, None))
+        rwg = np.zeros((n.value, 6), dtype=np.int32)
+        anc = np.zeros((n.value, 3), dtype=np.int32)
+        rowptr = np.zeros(n.value + 1, dtype=np.int64)
+        cols = np.zeros(max(nnz.value, 1), dtype=np.int32)
+        grid = np.zeros(3, dtype=np.int32)
+        pad = np.zeros(3, dtype=np.int32)
+        x0h = np.zeros(4, dtype=np.float64)
+        _check(L.aim_host_plan_export(
+            hp, None, None, rwg.ctypes.data_as(POINTER(c_int32)), anc.ctypes.data_as(POINTER(c_int32)),
+            rowptr.ctypes.data_as(POINTER(c_int64)), cols.ctypes.data_as(POINTER(c_int32)),
+            grid.ctypes.data_as(POINTER(c_int32)), pad.ctypes.data_as(POINTER(c_int32)),
+            x0h.ctypes.data_as(POINTER(c_double))))
+    finally:
+        L.aim_host_plan_destroy(hp)
+    return dict(n=n.value, nnz=nnz.value, rwg=rwg, anchors=anc, rowptr=rowptr,
+                cols=cols[:nnz.value], grid=grid, pad=pad, x0=x0h[:3], h=x0h[3])
+
+
+class TorchAllocator:
+    """Device memory for the library from PyTorch's caching allocator."""
+
+    def __init__(self, device):
+        import torch
+
+        self._torch = torch
+        self.device = device
+
+        def _alloc(ctx, nbytes, stream):
+            try:
+                return int(torch.cuda.caching_allocator_alloc(int(nbytes), self.device,
+                                                              int(stream or 0)))
+            except Exception:  # out of memory -> NULL, reported by the library
+                return None
+
+        def _free(ctx, ptr, stream):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        self._alloc = ALLOC_FN(_alloc)
+        self._free = FREE_FN(_free)
+        self.struct = AimAllocator(None, self._alloc, self._free)
+
+
+class Plan:
+    """An AIM operator on the current GPU for one or more meshes.
+
+    meshes: list of (verts (nv,3) metres, tris (nt,3), freq_hz)."""
+
+    def __init__(self, meshes, h_lambda=0.1, order=2, near_radius_lambda=0.3, fft_min_pad=0,
+                 mixed=True, stream=None):
+        import torch
+
+        self._torch = torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the AIM library needs a GPU")
+        self.device = torch.cuda.current_device()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        L = lib()
+        keep = []
+        arr = (AimMesh * len(meshes))()
+        for i, (v, t, f) in enumerate(meshes):
+            arr[i] = _mesh_struct(v, t, f, keep)
+        p = _params(h_lambda, order, near_radius_lambda, fft_min_pad, 0 if mixed else AIM_FLAG_NO_MIXED)
+        self._alloc = TorchAllocator(self.device)
+        h = c_void_p()
+        _check(L.aim_setup(arr, len(meshes), ctypes.byref(p), ctypes.byref(self._alloc.struct),
+                           c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.nmesh = len(meshes)
+        self._info = self.info()
+        self.n_total = self._info["n_total"]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._torch.cuda.synchronize()
+            lib().aim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = AimInfo()
+        _check(lib().aim_plan_info(self._h, ctypes.byref(inf)))
+        nm = inf.nmesh
+        return dict(
+            nmesh=nm, order=inf.order, n_total=inf.n_total, nnz_total=inf.nnz_total,
+            n=[inf.n[i] for i in range(nm)], offset=[inf.offset[i] for i in range(nm)],
+            nnz=[inf.nnz[i] for i in range(nm)], grid=[tuple(inf.grid[i]) for i in range(nm)],
+            pad=[tuple(inf.pad[i]) for i in range(nm)], h=[inf.h[i] for i in range(nm)],
+            x0=[tuple(inf.x0[i]) for i in range(nm)], k=[inf.k[i] for i in range(nm)],
+            bytes_fp64=[inf.bytes_fp64[i] for i in range(nm)],
+            bytes_mixed=[inf.bytes_mixed[i] for i in range(nm)], device_bytes=inf.device_bytes)
+
+    def _stream(self, stream):
+        s = stream if stream is not None else self._torch.cuda.current_stream()
+        return c_void_p(s.cuda_stream)
+
+    def matvec(self, x, precision=AIM_FP64, out=None, stream=None):
+        """y = Z x for x of shape (n_total,) or (nrhs, n_total): complex128 for
+        AIM_FP64, complex64 for AIM_MIXED (device tensors)."""
+        torch = self._torch
+        dt = torch.complex128 if precision == AIM_FP64 else torch.complex64
+        if x.dtype != dt or not x.is_cuda:
+            raise ValueError(f"x must be a {dt} device tensor")
+        xx = x.reshape(-1, self.n_total)
+        if not xx.is_contiguous():
+            raise ValueError("x must be contiguous")
+        y = out if out is not None else torch.empty_like(xx)
+        _check(lib().aim_matvec(self._h, precision, xx.shape[0], c_void_p(xx.data_ptr()),
+                                c_void_p(y.data_ptr()), self._stream(stream)))
+        return y.reshape(x.shape)
+
+    def matvec_raw(self, precision, nrhs, x_ptr, y_ptr, stream_ptr):
+        """aim_matvec on raw device pointers (timing loops)."""
+        _check(lib().aim_matvec(self._h, precision, nrhs, c_void_p(x_ptr), c_void_p(y_ptr),
+                                c_void_p(stream_ptr)))
+
+    def excitation(self, waves, stream=None):
+        torch = self._torch
+        arr = _waves(waves)
+        b = torch.empty((len(waves), self.n_total), dtype=torch.complex128, device="cuda")
+        _check(lib().aim_excitation(self._h, len(waves), arr, c_void_p(b.data_ptr()),
+                                    self._stream(stream)))
+        return b
+
+    def solve(self, waves, precision=AIM_MIXED, tol=1e-4, restart=100, max_iter=5000, x0=None,
+              stream=None, raise_on_noconv=True):
+        torch = self._torch
+        arr = _waves(waves)
+        R = len(waves)
+        if x0 is not None:
+            x = x0.to(torch.complex128).reshape(R, self.n_total).contiguous().clone()
+        else:
+            x = torch.zeros((R, self.n_total), dtype=torch.complex128, device="cuda")
+        opts = AimSolveOpts(float(tol), int(restart), int(max_iter), 1 if x0 is not None else 0, 0)
+        st = (AimSolveStats * R)()
+        status = lib().aim_gmres_solve(self._h, precision, R, arr, ctypes.byref(opts),
+                                       c_void_p(x.data_ptr()), st, self._stream(stream))
+        if status != AIM_OK and (status != AIM_ERR_NOCONV or raise_on_noconv):
+            _check(status)
+        stats = [dict(iterations=s.iterations, converged=bool(s.converged), matvec_low=s.matvec_low,
+                      matvec_fp64=s.matvec_fp64, residual=s.residual, seconds=s.seconds) for s in st]
+        return x, stats
+
+    def rcs(self, x, theta, phi, stream=None):
+        """sigma_tt (nmesh, nrhs, ntheta, nphi) in m^2 for currents x (nrhs, n_total)."""
+        torch = self._torch
+        xx = x.reshape(-1, self.n_total).to(torch.complex128).contiguous()
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        ph = np.ascontiguousarray(phi, dtype=np.float64)
+        out = np.zeros((self.nmesh, xx.shape[0], th.size, ph.size), dtype=np.float64)
+        _check(lib().aim_rcs(self._h, xx.shape[0], c_void_p(xx.data_ptr()), th.size,
+                             th.ctypes.data_as(POINTER(c_double)), ph.size,
+                             ph.ctypes.data_as(POINTER(c_double)),
+                             out.ctypes.data_as(POINTER(c_double)), self._stream(stream)))
+        return out
+
+    def export(self, mesh: int, what: int):
+        inf = self._info
+        n, nnz = inf["n"][mesh], inf["nnz"][mesh]
+        K = (inf["order"] + 1) ** 3
+        pad = inf["pad"][mesh]
+        if what == AIM_DATA_LAMBDA64:
+            out = np.zeros((n, 4, K), dtype=np.float64)
+        elif what == AIM_DATA_NEAR64:
+            out = np.zeros(nnz, dtype=np.complex128)
+        elif what == AIM_DATA_ZDIAG64:
+            out = np.zeros(n, dtype=np.complex128)
+        elif what == AIM_DATA_GHAT64:
+            out = np.zeros(tuple(p // 2 + 1 for p in pad), dtype=np.complex128)
+        else:
+            raise ValueError(what)
+        _check(lib().aim_export(self._h, mesh, what, c_void_p(out.ctypes.data), out.nbytes))
+        return out
+
+    def far_stage(self, mesh: int, x, stage: int, precision=AIM_FP64, stream=None):
+        """Grid buffer after `stage` (1 projection .. 6 inverse z pass) for x
+        (nrhs, n_total)."""
+        torch = self._torch
+        inf = self._info
+        Nx, Ny, Nz = inf["grid"][mesh]
+        Px, Py, Pz = inf["pad"][mesh]
+        shapes = {1: (Nx, Ny, Nz), 2: (Nx, Ny, Pz), 3: (Nx, Py, Pz), 4: (Nx, Py, Pz),
+                  5: (Nx, Ny, Pz), 6: (Nx, Ny, Nz)}
+        dt = torch.complex128 if precision == AIM_FP64 else torch.complex64
+        xx = x.reshape(-1, self.n_total).to(dt).contiguous()
+        R = xx.shape[0]
+        out = torch.empty((R, 4) + shapes[stage], dtype=dt, device="cuda")
+        _check(lib().aim_debug_far_stage(self._h, precision, mesh, R, c_void_p(xx.data_ptr()), stage,
+                                         c_void_p(out.data_ptr()), self._stream(stream)))
+        return out

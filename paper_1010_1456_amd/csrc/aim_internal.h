@@ -1,0 +1,172 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/aim.h"
+
+namespace aim {
+
+constexpr double kC0 = 299792458.0;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kMu0 = 4.0e-7 * kPi;
+constexpr double kEta0 = kMu0 * kC0;
+
+// Status-carrying exception used inside the library; converted to
+// aim_status at the ABI.
+struct Error : std::runtime_error {
+  aim_status status;
+  Error(aim_status s, const std::string &m) : std::runtime_error(m), status(s) {}
+};
+
+void hip_check(hipError_t e, const char *what, const char *file, int line);
+#define HIPCHECK(x) ::aim::hip_check((x), #x, __FILE__, __LINE__)
+#define LAUNCHCHECK() ::aim::hip_check(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
+
+// ---------------------------------------------------------------------------
+// FFT plans: length P factored into stages of supported radices.
+constexpr int kMaxStages = 4;
+struct FftPlan {
+  int P = 0;
+  int ns = 0;
+  int r[kMaxStages] = {0, 0, 0, 0};
+};
+bool fft_plan_for(int P, FftPlan *out);  // false if P has no supported factorisation
+int fft_length_at_least(int lo);        // smallest supported length >= lo
+
+// ---------------------------------------------------------------------------
+// Host plan of one mesh (no GPU involved).
+struct HostPlan {
+  int64_t nv = 0, nt = 0, n = 0, nnz = 0;
+  double freq = 0, lam = 0, k = 0, h = 0, r_near = 0;
+  int order = 2, K = 27;
+  std::vector<double> verts;     // nv*3
+  std::vector<int32_t> tris;     // nt*3
+  std::vector<double> area;      // nt
+  // RWG table, per unknown
+  std::vector<int32_t> e_lo, e_hi, tp, tm, vp, vm;
+  std::vector<double> len;       // edge length
+  std::vector<double> centre;    // n*3
+  // grid
+  int grid[3] = {0, 0, 0};
+  int pad[3] = {0, 0, 0};
+  double x0[3] = {0, 0, 0};
+  std::vector<int32_t> anchor;   // n*3
+  // near zone CSR
+  std::vector<int64_t> rowptr;   // n+1
+  std::vector<int32_t> cols;     // nnz
+};
+
+void host_plan_build(const aim_mesh &m, const aim_params &p, HostPlan *hp);
+
+// ---------------------------------------------------------------------------
+// Device-side data of one mesh.
+template <typename T>
+struct vec2_of;
+template <>
+struct vec2_of<float> {
+  using type = float2;
+};
+template <>
+struct vec2_of<double> {
+  using type = double2;
+};
+// interleaved complex value of real type T (float2 / double2)
+template <typename T>
+using cx = typename vec2_of<T>::type;
+
+struct MeshDev {
+  HostPlan hp;
+  int64_t offset = 0;
+  FftPlan plan[3];
+  int H[3] = {0, 0, 0};       // octant extents P_d/2 + 1
+  // geometry
+  double *verts = nullptr;    // nv*3
+  int32_t *tris = nullptr;    // nt*3
+  double *area = nullptr;     // nt
+  int32_t *rwg = nullptr;     // n*4: T+, T-, v+, v-
+  double *len = nullptr;      // n
+  int32_t *anchor_lin = nullptr;  // n: linear index of the stencil corner
+  // operator
+  double *lam64 = nullptr;    // n*4*K
+  float *lam32 = nullptr;
+  int32_t *rowptr = nullptr;  // n+1
+  int32_t *cols = nullptr;    // nnz
+  double2 *near64 = nullptr;  // nnz
+  float2 *near32 = nullptr;
+  double2 *zdiag = nullptr;   // n (diag of Z^MOM)
+  double2 *ghat64 = nullptr;  // H0*H1*H2
+  float2 *ghat32 = nullptr;
+  double2 *tw64[3] = {nullptr, nullptr, nullptr};  // twiddles exp(-2 pi i e / P_d)
+  float2 *tw32[3] = {nullptr, nullptr, nullptr};
+  int32_t *stencil_off = nullptr;  // K linear offsets
+};
+
+struct Plan;
+
+// Device memory through the plan's allocator.
+void *dev_alloc(Plan *pl, size_t bytes);
+void dev_free(Plan *pl, void *p);
+
+struct Plan {
+  aim_allocator alloc{};
+  bool own_alloc = true;
+  hipStream_t setup_stream = nullptr;
+  aim_params params{};
+  bool mixed = true;
+  int nmesh = 0;
+  int64_t n_total = 0;
+  std::vector<MeshDev> mesh;
+  std::vector<std::pair<void *, size_t>> live;  // allocations (for destroy/info)
+  double device_bytes = 0;
+  // grid work buffers (per precision), grown on demand
+  void *work[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  size_t work_bytes[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  // solver scratch
+  void *solver_buf = nullptr;
+  size_t solver_bytes = 0;
+};
+
+// set-up kernels (setup_kernels.hip)
+void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s);
+
+// FFT passes (fft_*.hip); one overload per precision, dispatching on pl.P
+#define AIM_DECLARE_FFT(V)                                                                       \
+  void fft_pass_contig(const V *in, V *out, const FftPlan &pl, int n_in, int n_out,              \
+                       int64_t lines, int64_t in_line_stride, int64_t out_line_stride,           \
+                       bool inverse, const V *tw, hipStream_t s);                                \
+  void fft_pass_strided(const V *in, V *out, const FftPlan &pl, int n_in, int n_out,             \
+                        int64_t outer, int64_t inner, int64_t in_elem, int64_t in_outer,         \
+                        int64_t out_elem, int64_t out_outer, bool inverse, const V *tw,          \
+                        hipStream_t s);                                                          \
+  void fft_mid_pass(V *data, const FftPlan &pl, int n_x, int nfield, int Py, int Pz, int Hx,     \
+                    int Hy, int Hz, const V *ghat, const V *tw, hipStream_t s);
+AIM_DECLARE_FFT(float2)
+AIM_DECLARE_FFT(double2)
+#undef AIM_DECLARE_FFT
+
+// matvec (matvec.hip)
+template <typename T, typename TX>
+void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, int stop_stage,
+                hipStream_t s);
+template <typename T, typename TX, typename TY>
+void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, cx<TY> *y,
+                 int64_t ldy, hipStream_t s);
+void *work_buffer(Plan *pl, int prec, int which, size_t bytes);
+
+// excitation / rcs (setup_kernels.hip, rcs.hip)
+void excitation_mesh(Plan *pl, MeshDev &md, int nw, const aim_planewave *w, double2 *b, int64_t ldb,
+                     hipStream_t s);
+void rcs_mesh(Plan *pl, MeshDev &md, int nrhs, const double2 *x, int64_t ldx, int ntheta,
+              const double *theta, int nphi, const double *phi, double *sigma, hipStream_t s);
+
+// solver (solver.hip)
+aim_status gmres_solve(Plan *pl, aim_precision prec, int nrhs, const aim_planewave *waves,
+                       const aim_solve_opts &o, double2 *x, aim_solve_stats *st, hipStream_t s);
+
+}  // namespace aim

@@ -1,0 +1,22 @@
+// FFT pass dispatch for double2: the run-time length selects the compiled kernel set.
+#include "fft_kernels.h"
+
+namespace aim {
+void fft_pass_contig(const double2 *in, double2 *out, const FftPlan &pl, int n_in, int n_out,
+                     int64_t lines, int64_t in_ls, int64_t out_ls, bool inverse, const double2 *tw,
+                     hipStream_t s) {
+  if (lines <= 0) return;
+  switch (pl.P) {
+#define AIM_X(P, a, b, c)                                                                     \
+  case P:                                                                                     \
+    fftk::launch_contig<double, fftk::PlanC<a, b, c>>(in, out, n_in, n_out, lines, in_ls, out_ls, \
+                                                   inverse, tw, s);                           \
+    return;
+    AIM_FOR_EACH_FFT_PLAN(AIM_X)
+#undef AIM_X
+    default:
+      break;
+  }
+  fftk::bad_length(pl.P);
+}
+}  // namespace aim

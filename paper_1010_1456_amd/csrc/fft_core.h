@@ -1,0 +1,268 @@
+// Register-level FFT building blocks for the grid passes.
+//
+// A length-P transform is factored into stages of radix r (Stockham
+// autosort). With L the product of the radices already applied and
+// M' = P / (L r), butterfly beta = j M' + k' (j < L, k' < M') of a stage reads
+//     x[j r M' + q M' + k'],               q = 0..r-1,
+// multiplies element q by exp(-+2 pi i j q M' / P), applies a length-r DFT and
+// writes element p to
+//     x[(j + L p) M' + k'],                p = 0..r-1.
+// The first stage (L = 1) reads plain strided input; the last (M' = 1) writes
+// natural order. Small DFTs are unrolled at compile time: primes 2, 3, 5, 7
+// directly, composite radices as two smaller DFTs with compile-time twiddles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+#define AIM_AI __attribute__((always_inline))
+
+namespace aim {
+namespace fftc {
+
+// ---- compile-time trigonometry (Taylor series after reduction to [-pi, pi])
+constexpr double kPiD = 3.14159265358979323846264338327950288;
+
+constexpr double ce_reduce(double x) {
+  while (x > kPiD) x -= 2.0 * kPiD;
+  while (x < -kPiD) x += 2.0 * kPiD;
+  return x;
+}
+constexpr double ce_sin(double x) {
+  x = ce_reduce(x);
+  double term = x, sum = x;
+  for (int n = 1; n < 30; ++n) {
+    term *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double ce_cos(double x) {
+  x = ce_reduce(x);
+  double term = 1.0, sum = 1.0;
+  for (int n = 1; n < 30; ++n) {
+    term *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+    sum += term;
+  }
+  return sum;
+}
+
+template <int N, typename F, int... Is>
+__host__ __device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__host__ __device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
+
+template <typename V>
+struct real_of;
+template <>
+struct real_of<float2> {
+  using type = float;
+};
+template <>
+struct real_of<double2> {
+  using type = double;
+};
+
+template <typename V>
+__host__ __device__ __forceinline__ V mk(typename real_of<V>::type x, typename real_of<V>::type y) {
+  V v;
+  v.x = x;
+  v.y = y;
+  return v;
+}
+template <typename V>
+__host__ __device__ __forceinline__ V add(V a, V b) {
+  return mk<V>(a.x + b.x, a.y + b.y);
+}
+template <typename V>
+__host__ __device__ __forceinline__ V sub(V a, V b) {
+  return mk<V>(a.x - b.x, a.y - b.y);
+}
+template <typename V>
+__host__ __device__ __forceinline__ V cmul(V a, V b) {
+  return mk<V>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename V>
+__host__ __device__ __forceinline__ V cmulc(V a, V b) {  // a * conj(b)
+  return mk<V>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+// multiply by -i (forward sense) or +i (inverse sense)
+template <bool INV, typename V>
+__host__ __device__ __forceinline__ V mul_mi(V a) {
+  return INV ? mk<V>(-a.y, a.x) : mk<V>(a.y, -a.x);
+}
+
+// a * exp(-+ 2 pi i E / R), E and R compile-time
+template <int R, int E, bool INV, typename V>
+__host__ __device__ __forceinline__ V twc(V a) {
+  using T = typename real_of<V>::type;
+  constexpr int e = ((E % R) + R) % R;
+  if constexpr (e == 0) {
+    return a;
+  } else if constexpr (2 * e == R) {
+    return mk<V>(-a.x, -a.y);
+  } else if constexpr (4 * e == R) {
+    return mul_mi<INV>(a);
+  } else if constexpr (4 * e == 3 * R) {
+    return mul_mi<!INV>(a);
+  } else {
+    constexpr double ang = 2.0 * kPiD * (double)e / (double)R;
+    constexpr double c = ce_cos(ang);
+    constexpr double s = INV ? ce_sin(ang) : -ce_sin(ang);
+    return mk<V>((T)c * a.x - (T)s * a.y, (T)c * a.y + (T)s * a.x);
+  }
+}
+
+constexpr int smallest_factor(int n) {
+  for (int f = 2; f * f <= n; ++f)
+    if (n % f == 0) return f;
+  return n;
+}
+
+template <int R, bool INV, typename V, typename Enable = void>
+struct Dft;
+
+template <bool INV, typename V>
+struct Dft<1, INV, V> {
+  __host__ __device__ __forceinline__ static void run(V *) {}
+};
+
+template <bool INV, typename V>
+struct Dft<2, INV, V> {
+  __host__ __device__ __forceinline__ static void run(V *v) {
+    V a = v[0], b = v[1];
+    v[0] = add(a, b);
+    v[1] = sub(a, b);
+  }
+};
+
+template <bool INV, typename V>
+struct Dft<3, INV, V> {
+  __host__ __device__ __forceinline__ static void run(V *v) {
+    using T = typename real_of<V>::type;
+    const T s3 = (T)0.86602540378443864676372317075294;
+    V t1 = add(v[1], v[2]);
+    V d = sub(v[1], v[2]);
+    V t2 = mk<V>(v[0].x - (T)0.5 * t1.x, v[0].y - (T)0.5 * t1.y);
+    V rot = mul_mi<INV>(mk<V>(s3 * d.x, s3 * d.y));  // -+ i s3 (v1 - v2)
+    v[0] = add(v[0], t1);
+    v[1] = add(t2, rot);
+    v[2] = sub(t2, rot);
+  }
+};
+
+// odd prime R: symmetric pairs a_m = v_m + v_{R-m}, b_m = v_m - v_{R-m};
+// X_k = v0 + sum_m a_m cos(2 pi k m / R) -+ i sum_m b_m sin(2 pi k m / R)
+template <int R, bool INV, typename V>
+struct DftOddPrime {
+  __host__ __device__ __forceinline__ static void run(V *v) {
+    using T = typename real_of<V>::type;
+    constexpr int H = (R - 1) / 2;
+    V a[H], b[H];
+    static_for<H>([&](auto m_) AIM_AI {
+      constexpr int m = decltype(m_)::value + 1;
+      a[m - 1] = add(v[m], v[R - m]);
+      b[m - 1] = sub(v[m], v[R - m]);
+    });
+    V x0 = v[0];
+    V sum = x0;
+    static_for<H>([&](auto m_) AIM_AI { sum = add(sum, a[decltype(m_)::value]); });
+    V out[R];
+    out[0] = sum;
+    static_for<H>([&](auto k_) AIM_AI {
+      constexpr int k = decltype(k_)::value + 1;
+      V re = x0, im = mk<V>((T)0, (T)0);
+      static_for<H>([&](auto m_) AIM_AI {
+        constexpr int m = decltype(m_)::value + 1;
+        constexpr double c = ce_cos(2.0 * kPiD * (double)(k * m % R) / (double)R);
+        constexpr double s = ce_sin(2.0 * kPiD * (double)(k * m % R) / (double)R);
+        re = mk<V>(re.x + (T)c * a[m - 1].x, re.y + (T)c * a[m - 1].y);
+        im = mk<V>(im.x + (T)s * b[m - 1].x, im.y + (T)s * b[m - 1].y);
+      });
+      V rot = mul_mi<INV>(im);  // -+ i * im
+      out[k] = add(re, rot);
+      out[R - k] = sub(re, rot);
+    });
+    static_for<R>([&](auto i_) AIM_AI { v[decltype(i_)::value] = out[decltype(i_)::value]; });
+  }
+};
+
+template <bool INV, typename V>
+struct Dft<5, INV, V> : DftOddPrime<5, INV, V> {};
+template <bool INV, typename V>
+struct Dft<7, INV, V> : DftOddPrime<7, INV, V> {};
+
+// composite R = A * B, A the smallest prime factor: stage 1 runs B DFTs of
+// length A (L = 1, M' = B), stage 2 runs A DFTs of length B (L = A, M' = 1)
+template <int R, bool INV, typename V>
+struct Dft<R, INV, V, std::enable_if_t<(R > 3 && smallest_factor(R) != R)>> {
+  __host__ __device__ __forceinline__ static void run(V *v) {
+    constexpr int A = smallest_factor(R);
+    constexpr int B = R / A;
+    V u[R];
+    static_for<B>([&](auto kp_) AIM_AI {
+      constexpr int kp = decltype(kp_)::value;
+      V s[A];
+      static_for<A>([&](auto q_) AIM_AI { s[decltype(q_)::value] = v[decltype(q_)::value * B + kp]; });
+      Dft<A, INV, V>::run(s);
+      static_for<A>([&](auto p_) AIM_AI { u[decltype(p_)::value * B + kp] = s[decltype(p_)::value]; });
+    });
+    static_for<A>([&](auto j_) AIM_AI {
+      constexpr int j = decltype(j_)::value;
+      V s[B];
+      static_for<B>([&](auto q_) AIM_AI {
+        constexpr int q = decltype(q_)::value;
+        s[q] = twc<R, j * q, INV>(u[j * B + q]);
+      });
+      Dft<B, INV, V>::run(s);
+      static_for<B>([&](auto p_) AIM_AI { v[j + A * decltype(p_)::value] = s[decltype(p_)::value]; });
+    });
+  }
+};
+
+// Twiddle exp(-+ 2 pi i e / P) from a table of exp(-2 pi i e / P).
+template <bool INV, typename V>
+__host__ __device__ __forceinline__ V tw_mul(V a, const V *tw, int e) {
+  V w = tw[e];
+  return INV ? cmulc(a, w) : cmul(a, w);
+}
+
+// One Stockham stage for butterfly beta. ld(i) / st(i, v) access element i
+// of the line. Barrier placement is the caller's.
+template <int R, bool INV, typename V, class Ld>
+__device__ __forceinline__ void stage_load(V *v, int beta, int Mp, Ld &ld) {
+  int j = beta / Mp, kp = beta - j * Mp;
+  int base = j * R * Mp + kp;
+  static_for<R>([&](auto q_) AIM_AI { v[decltype(q_)::value] = ld(base + decltype(q_)::value * Mp); });
+}
+
+template <int R, bool INV, typename V, class St>
+__device__ __forceinline__ void stage_compute_store(V *v, int beta, int L, int Mp, const V *tw,
+                                                    St &st) {
+  int j = beta / Mp, kp = beta - j * Mp;
+  if (L > 1) {
+    int step = j * Mp;
+    static_for<R - 1>([&](auto q_) AIM_AI {
+      constexpr int q = decltype(q_)::value + 1;
+      v[q] = tw_mul<INV>(v[q], tw, step * q);
+    });
+  }
+  Dft<R, INV, V>::run(v);
+  static_for<R>([&](auto p_) AIM_AI {
+    constexpr int p = decltype(p_)::value;
+    st((j + L * p) * Mp + kp, v[p]);
+  });
+}
+
+// Supported radices; the dispatch macro expands a body once per radix with
+// the constant RADIX defined.
+#define AIM_FOR_EACH_RADIX(X) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(12) X(14) X(16) X(18)
+
+}  // namespace fftc
+}  // namespace aim

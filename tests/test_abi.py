@@ -1,0 +1,100 @@
+"""C ABI checks that need no GPU: exported symbols, host planning against the
+oracle (bit-exact integer decisions), error paths."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import aim as oaim
+from oracle.rwg import build_rwg
+from paper_1010_1456_amd import aim as lib_aim
+from workloads import plate_mesh, sphere_mesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "aim.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(aim_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lib_aim.lib()
+    declared = _declared_symbols()
+    assert len(declared) >= 10
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(lib_aim.EXPORTED) == declared
+
+
+def _compare_host_plan(mesh, h=0.1, M=2, rn=0.3):
+    hp = lib_aim.host_plan(mesh.verts, mesh.tris, mesh.freq_hz, h, M, rn)
+    rwg = build_rwg(mesh.verts, mesh.tris)
+    g = oaim.grid_plan(rwg.verts, h * mesh.lam, M)
+    anc = oaim.anchors(g, rwg.centre)
+    ip, ix = oaim.near_pairs(rwg.centre, rn * mesh.lam)
+    assert hp["n"] == rwg.n
+    assert np.array_equal(hp["rwg"][:, 0:2], rwg.edge)
+    assert np.array_equal(hp["rwg"][:, 2], rwg.tplus)
+    assert np.array_equal(hp["rwg"][:, 3], rwg.tminus)
+    assert np.array_equal(hp["rwg"][:, 4], rwg.vplus)
+    assert np.array_equal(hp["rwg"][:, 5], rwg.vminus)
+    assert np.array_equal(hp["grid"], g.n)
+    assert np.array_equal(hp["x0"], g.x0)
+    assert hp["h"] == g.h
+    assert np.array_equal(hp["anchors"], anc)
+    assert np.array_equal(hp["rowptr"], ip)
+    assert np.array_equal(hp["cols"], ix)
+    assert np.all(hp["pad"] >= 2 * hp["grid"] - 1)
+    return hp
+
+
+@pytest.mark.parametrize("mesh", [
+    plate_mesh(1.0, 0.3e9), plate_mesh(4.0, 1.2e9, jitter_seed=1002), sphere_mesh(1.0, 0.3e9, nf=11),
+    sphere_mesh(2.0, 0.6e9, nf=22, jitter_seed=1005)], ids=["plate1", "plate4j", "sphere1", "sphere2j"])
+def test_host_plan_matches_oracle(mesh):
+    _compare_host_plan(mesh)
+
+
+def test_host_plan_plate16_counts():
+    """16-lambda plate: 61,920 unknowns, 161x161x3 grid, near pattern equal
+    to the oracle's (integer-exact)."""
+    hp = _compare_host_plan(plate_mesh(16.0, 4.8e9))
+    assert hp["n"] == 61920
+    assert tuple(hp["grid"]) == (161, 161, 3)
+
+
+def test_host_plan_other_orders():
+    m = sphere_mesh(0.5, 0.3e9, nf=4)
+    for M in (1, 3):
+        _compare_host_plan(m, h=0.08, M=M, rn=0.25)
+
+
+def test_error_paths():
+    v = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 1]], dtype=float)
+    with pytest.raises(lib_aim.AimError) as e:
+        lib_aim.host_plan(v, np.array([[0, 1, 2], [0, 1, 3], [1, 0, 4]]), 0.3e9)
+    assert e.value.status == lib_aim.AIM_ERR_MESH
+    with pytest.raises(lib_aim.AimError) as e:
+        lib_aim.host_plan(v, np.array([[0, 1, 7]]), 0.3e9)
+    assert e.value.status == lib_aim.AIM_ERR_MESH
+    with pytest.raises(lib_aim.AimError) as e:
+        lib_aim.host_plan(np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0]], float), np.array([[0, 1, 2]]), 0.3e9)
+    assert e.value.status == lib_aim.AIM_ERR_MESH
+    m = plate_mesh(1.0, 0.3e9)
+    with pytest.raises(lib_aim.AimError) as e:
+        lib_aim.host_plan(m.verts, m.tris, -1.0)
+    assert e.value.status == lib_aim.AIM_ERR_ARG
+    with pytest.raises(lib_aim.AimError) as e:
+        lib_aim.host_plan(m.verts, m.tris, m.freq_hz, h_lambda=0.0)
+    assert e.value.status == lib_aim.AIM_ERR_ARG
+    with pytest.raises(lib_aim.AimError) as e:
+        lib_aim.host_plan(m.verts, m.tris, m.freq_hz, order=0)
+    assert e.value.status == lib_aim.AIM_ERR_ARG
+    # a single triangle has no interior edge
+    with pytest.raises(lib_aim.AimError) as e:
+        lib_aim.host_plan(v[:3], np.array([[0, 1, 2]]), 0.3e9)
+    assert e.value.status == lib_aim.AIM_ERR_MESH
