@@ -54,7 +54,10 @@ typedef enum {
  * AIM_MIXED: the same steps in complex float (operator data rounded from the
  *            FP64 set-up); the solver keeps FP64 Krylov vectors and an FP64
  *            outer residual (iterative refinement). */
-typedef enum { AIM_FP64 = 0, AIM_MIXED = 1 } aim_precision;
+typedef enum { AIM_FP64 = 0, AIM_MIXED = 1, AIM_MIXED_IO64 = 2 } aim_precision;
+/* AIM_MIXED_IO64: the AIM_MIXED arithmetic on c128 input/output vectors,
+ * narrowed and widened in registers (how the solver applies the c64 operator
+ * to its FP64 Krylov vectors). Accepted by aim_matvec and aim_matvec_timed. */
 
 /* A PEC triangle surface (paper Section 2.1). Host memory, copied by
  * aim_setup/aim_host_plan; the caller may free it afterwards.
@@ -180,6 +183,21 @@ void aim_destroy(aim_plan *plan);
  * x and y must not overlap. */
 aim_status aim_matvec(aim_plan *plan, aim_precision prec, int32_t nrhs,
                       const void *x, void *y, void *hip_stream);
+
+/* Runs nrep products y = Z^AIM x back to back on hip_stream with HIP events
+ * between the kernels of every product, then synchronises. x, y as for
+ * aim_matvec (c128 for AIM_FP64 and AIM_MIXED_IO64, c64 for AIM_MIXED).
+ * stage_ms (host, AIM_NSTAGE doubles, may be NULL) receives the summed event
+ * time of each step over all repetitions and meshes:
+ *   0 projection (grid clear + anterpolation), 1 forward z pass,
+ *   2 forward y pass, 3 x pass with the Green's spectrum multiply,
+ *   4 inverse y pass, 5 inverse z pass, 6 interpolation + near correction;
+ * total_ms (host, may be NULL) the event time from the first to the last
+ * kernel. */
+#define AIM_NSTAGE 7
+aim_status aim_matvec_timed(aim_plan *plan, aim_precision prec, int32_t nrhs, const void *x,
+                            void *y, int32_t nrep, double *stage_ms, double *total_ms,
+                            void *hip_stream);
 
 /* Solves Z^AIM x = b for nrhs_per_mesh plane waves on every mesh of the plan
  * (waves: host, nrhs_per_mesh entries, the same set for every mesh) with

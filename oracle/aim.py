@@ -31,6 +31,8 @@ Product. y = Z^near x + j k eta [ sum_q Lambda_q^T (g * Lambda_q x)
   - k^-2 Lambda_d^T (g * Lambda_d x) ], where * is the discrete convolution
   over grid nodes: ``matvec_direct`` sums it directly over occupied nodes,
   ``matvec_fft`` evaluates it by zero-padded FFTs of any size P_d >= 2N_d - 1.
+
+FFT thread count follows ``scipy.fft.set_workers`` (default: one worker).
 """
 
 from __future__ import annotations
@@ -268,7 +270,7 @@ def green_spectrum(k: float, grid: Grid, pad) -> np.ndarray:
     V = idx[0][1][:, None, None] & idx[1][1][None, :, None] & idx[2][1][None, None, :]
     gemb = grid_green(k, grid.h, np.stack([I, J, K], axis=-1))
     gemb[~V] = 0.0
-    return scipy.fft.fftn(gemb, workers=-1)
+    return scipy.fft.fftn(gemb)
 
 
 def convolve_fft(op: AIMOperator, s: np.ndarray, pad=None, ghat=None) -> np.ndarray:
@@ -281,8 +283,8 @@ def convolve_fft(op: AIMOperator, s: np.ndarray, pad=None, ghat=None) -> np.ndar
     phi = np.zeros_like(s)
     for r in range(s.shape[0]):
         for q in range(4):
-            S = scipy.fft.fftn(s[r, q].reshape(n), s=pad, workers=-1)
-            out = scipy.fft.ifftn(S * ghat, workers=-1)
+            S = scipy.fft.fftn(s[r, q].reshape(n), s=pad)
+            out = scipy.fft.ifftn(S * ghat)
             phi[r, q] = out[:n[0], :n[1], :n[2]].ravel()
     return phi
 

@@ -26,6 +26,8 @@ AIM_ERR_NOCONV = -5
 AIM_ERR_STATE = -6
 AIM_FP64 = 0
 AIM_MIXED = 1
+AIM_MIXED_IO64 = 2
+AIM_NSTAGE = 7
 AIM_FLAG_NO_MIXED = 1
 AIM_MAX_MESH = 16
 AIM_DATA_LAMBDA64 = 1
@@ -34,7 +36,7 @@ AIM_DATA_ZDIAG64 = 3
 AIM_DATA_GHAT64 = 4
 
 EXPORTED = [
-    "aim_setup", "aim_plan_info", "aim_destroy", "aim_matvec", "aim_gmres_solve",
+    "aim_setup", "aim_plan_info", "aim_destroy", "aim_matvec", "aim_matvec_timed", "aim_gmres_solve",
     "aim_excitation", "aim_rcs", "aim_host_plan_build", "aim_host_plan_export",
     "aim_host_plan_destroy", "aim_export", "aim_debug_far_stage", "aim_last_error",
 ]
@@ -105,6 +107,8 @@ def lib():
         "aim_setup": [POINTER(AimMesh), c_int32, POINTER(AimParams), POINTER(AimAllocator), P, POINTER(P)],
         "aim_plan_info": [P, POINTER(AimInfo)],
         "aim_matvec": [P, c_int32, c_int32, P, P, P],
+        "aim_matvec_timed": [P, c_int32, c_int32, P, P, c_int32, POINTER(c_double),
+                             POINTER(c_double), P],
         "aim_gmres_solve": [P, c_int32, c_int32, POINTER(AimPlanewave), POINTER(AimSolveOpts), P,
                             POINTER(AimSolveStats), P],
         "aim_excitation": [P, c_int32, POINTER(AimPlanewave), P, P],
@@ -271,9 +275,9 @@ class Plan:
 
     def matvec(self, x, precision=AIM_FP64, out=None, stream=None):
         """y = Z x for x of shape (n_total,) or (nrhs, n_total): complex128 for
-        AIM_FP64, complex64 for AIM_MIXED (device tensors)."""
+        AIM_FP64 and AIM_MIXED_IO64, complex64 for AIM_MIXED (device tensors)."""
         torch = self._torch
-        dt = torch.complex128 if precision == AIM_FP64 else torch.complex64
+        dt = torch.complex64 if precision == AIM_MIXED else torch.complex128
         if x.dtype != dt or not x.is_cuda:
             raise ValueError(f"x must be a {dt} device tensor")
         xx = x.reshape(-1, self.n_total)
@@ -284,10 +288,16 @@ class Plan:
                                 c_void_p(y.data_ptr()), self._stream(stream)))
         return y.reshape(x.shape)
 
-    def matvec_raw(self, precision, nrhs, x_ptr, y_ptr, stream_ptr):
-        """aim_matvec on raw device pointers (timing loops)."""
-        _check(lib().aim_matvec(self._h, precision, nrhs, c_void_p(x_ptr), c_void_p(y_ptr),
-                                c_void_p(stream_ptr)))
+    def matvec_timed(self, x, y, precision, nrep, stream=None):
+        """nrep products with HIP events between the kernels; returns
+        (per-stage summed ms (AIM_NSTAGE,), first-to-last event ms)."""
+        st = (c_double * AIM_NSTAGE)()
+        tot = c_double()
+        nrhs = x.numel() // self.n_total
+        _check(lib().aim_matvec_timed(self._h, precision, nrhs, c_void_p(x.data_ptr()),
+                                      c_void_p(y.data_ptr()), int(nrep), st, ctypes.byref(tot),
+                                      self._stream(stream)))
+        return np.array(st[:]), tot.value
 
     def excitation(self, waves, stream=None):
         torch = self._torch

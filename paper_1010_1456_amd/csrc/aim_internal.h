@@ -80,6 +80,11 @@ struct vec2_of<double> {
 template <typename T>
 using cx = typename vec2_of<T>::type;
 
+// kz run length of the blocked grid between the y passes and the x pass:
+// 128 bytes of complex values
+template <typename T>
+constexpr int kGridBlock = 128 / (int)sizeof(cx<T>);
+
 struct MeshDev {
   HostPlan hp;
   int64_t offset = 0;
@@ -105,6 +110,14 @@ struct MeshDev {
   double2 *tw64[3] = {nullptr, nullptr, nullptr};  // twiddles exp(-2 pi i e / P_d)
   float2 *tw32[3] = {nullptr, nullptr, nullptr};
   int32_t *stencil_off = nullptr;  // K linear offsets
+  // projection transposed to grid-node order (entries with a non-zero
+  // weight only): entries of node v are node_ptr[v] .. node_ptr[v+1]-1, each
+  // with its basis index and its 4 weights (x, y, z, div)
+  int64_t n_entries = 0;
+  int32_t *node_ptr = nullptr;  // V0 + 1
+  int32_t *ent_col = nullptr;   // n_entries
+  double *lamT64 = nullptr;     // n_entries * 4
+  float *lamT32 = nullptr;      // n_entries * 4
 };
 
 struct Plan;
@@ -135,29 +148,38 @@ struct Plan {
 // set-up kernels (setup_kernels.hip)
 void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s);
 
+namespace fftk {
+struct LineMap;
+}
+
 // FFT passes (fft_*.hip); one overload per precision, dispatching on pl.P
 #define AIM_DECLARE_FFT(V)                                                                       \
   void fft_pass_contig(const V *in, V *out, const FftPlan &pl, int n_in, int n_out,              \
                        int64_t lines, int64_t in_line_stride, int64_t out_line_stride,           \
                        bool inverse, const V *tw, hipStream_t s);                                \
   void fft_pass_strided(const V *in, V *out, const FftPlan &pl, int n_in, int n_out,             \
-                        int64_t outer, int64_t inner, int64_t in_elem, int64_t in_outer,         \
-                        int64_t out_elem, int64_t out_outer, bool inverse, const V *tw,          \
-                        hipStream_t s);                                                          \
+                        int64_t outer, int64_t inner, const fftk::LineMap &imap,                 \
+                        const fftk::LineMap &omap, bool inverse, const V *tw, hipStream_t s);    \
   void fft_mid_pass(V *data, const FftPlan &pl, int n_x, int nfield, int Py, int Pz, int Hx,     \
-                    int Hy, int Hz, const V *ghat, const V *tw, hipStream_t s);
+                    int Hy, int Hz, const V *ghat, const V *tw, int blk, int64_t fstride,        \
+                    hipStream_t s);
 AIM_DECLARE_FFT(float2)
 AIM_DECLARE_FFT(double2)
 #undef AIM_DECLARE_FFT
 
 // matvec (matvec.hip)
+// `ev` (optional) receives an event record before the first kernel and after
+// each stage: ev[0] .. ev[AIM_NSTAGE].
 template <typename T, typename TX>
 void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, int stop_stage,
-                hipStream_t s);
+                hipStream_t s, hipEvent_t *ev = nullptr);
 template <typename T, typename TX, typename TY>
 void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, cx<TY> *y,
-                 int64_t ldy, hipStream_t s);
+                 int64_t ldy, hipStream_t s, hipEvent_t *ev = nullptr);
 void *work_buffer(Plan *pl, int prec, int which, size_t bytes);
+// copies the grid buffer after far stage `stage` to out in plain layout
+template <typename T>
+void copy_far_stage(Plan *pl, MeshDev &md, int nrhs, int stage, void *out, hipStream_t s);
 
 // excitation / rcs (setup_kernels.hip, rcs.hip)
 void excitation_mesh(Plan *pl, MeshDev &md, int nw, const aim_planewave *w, double2 *b, int64_t ldb,

@@ -215,24 +215,88 @@ void aim_destroy(aim_plan *plan) {
   delete plan;
 }
 
-aim_status aim_matvec(aim_plan *plan, aim_precision prec, int32_t nrhs, const void *x, void *y,
-                      void *hip_stream) {
+static aim_status matvec_check(aim_plan *plan, aim_precision prec, int32_t nrhs, const void *x,
+                               void *y) {
   if (!plan || !x || !y) return fail(AIM_ERR_ARG, "NULL argument");
   if (nrhs < 1) return fail(AIM_ERR_ARG, "nrhs must be >= 1");
-  if (prec != AIM_FP64 && prec != AIM_MIXED) return fail(AIM_ERR_ARG, "bad precision");
-  if (prec == AIM_MIXED && !plan->mixed) return fail(AIM_ERR_STATE, "plan has no FP32 data");
+  if (prec != AIM_FP64 && prec != AIM_MIXED && prec != AIM_MIXED_IO64)
+    return fail(AIM_ERR_ARG, "bad precision");
+  if (prec != AIM_FP64 && !plan->mixed) return fail(AIM_ERR_STATE, "plan has no FP32 data");
+  return AIM_OK;
+}
+
+static void matvec_all(aim_plan *plan, aim_precision prec, int32_t nrhs, const void *x, void *y,
+                       hipStream_t s, hipEvent_t *ev) {
+  const int64_t ld = plan->n_total;
+  for (auto &md : plan->mesh) {
+    if (prec == AIM_FP64)
+      matvec_mesh<double, double, double>(plan, md, nrhs, (const double2 *)x + md.offset, ld,
+                                          (double2 *)y + md.offset, ld, s, ev);
+    else if (prec == AIM_MIXED)
+      matvec_mesh<float, float, float>(plan, md, nrhs, (const float2 *)x + md.offset, ld,
+                                       (float2 *)y + md.offset, ld, s, ev);
+    else
+      matvec_mesh<float, double, double>(plan, md, nrhs, (const double2 *)x + md.offset, ld,
+                                         (double2 *)y + md.offset, ld, s, ev);
+  }
+}
+
+aim_status aim_matvec(aim_plan *plan, aim_precision prec, int32_t nrhs, const void *x, void *y,
+                      void *hip_stream) {
+  aim_status st = matvec_check(plan, prec, nrhs, x, y);
+  if (st != AIM_OK) return st;
+  return guarded([&] { matvec_all(plan, prec, nrhs, x, y, (hipStream_t)hip_stream, nullptr); });
+}
+
+aim_status aim_matvec_timed(aim_plan *plan, aim_precision prec, int32_t nrhs, const void *x,
+                            void *y, int32_t nrep, double *stage_ms, double *total_ms,
+                            void *hip_stream) {
+  aim_status st = matvec_check(plan, prec, nrhs, x, y);
+  if (st != AIM_OK) return st;
+  if (nrep < 1) return fail(AIM_ERR_ARG, "nrep must be >= 1");
   hipStream_t s = (hipStream_t)hip_stream;
-  return guarded([&] {
+  // one event set per (repetition, mesh) so that no event is re-recorded
+  // before it has been read
+  const int nm = plan->nmesh;
+  std::vector<hipEvent_t> ev((size_t)nrep * nm * (AIM_NSTAGE + 1), nullptr);
+  aim_status r = guarded([&] {
+    for (auto &e : ev) HIPCHECK(hipEventCreate(&e));
     const int64_t ld = plan->n_total;
-    for (auto &md : plan->mesh) {
-      if (prec == AIM_FP64)
-        matvec_mesh<double, double, double>(plan, md, nrhs, (const double2 *)x + md.offset, ld,
-                                            (double2 *)y + md.offset, ld, s);
-      else
-        matvec_mesh<float, float, float>(plan, md, nrhs, (const float2 *)x + md.offset, ld,
-                                         (float2 *)y + md.offset, ld, s);
+    for (int rep = 0; rep < nrep; ++rep) {
+      int mi = 0;
+      for (auto &md : plan->mesh) {
+        hipEvent_t *e = &ev[((size_t)rep * nm + mi) * (AIM_NSTAGE + 1)];
+        if (prec == AIM_FP64)
+          matvec_mesh<double, double, double>(plan, md, nrhs, (const double2 *)x + md.offset, ld,
+                                              (double2 *)y + md.offset, ld, s, e);
+        else if (prec == AIM_MIXED)
+          matvec_mesh<float, float, float>(plan, md, nrhs, (const float2 *)x + md.offset, ld,
+                                           (float2 *)y + md.offset, ld, s, e);
+        else
+          matvec_mesh<float, double, double>(plan, md, nrhs, (const double2 *)x + md.offset, ld,
+                                             (double2 *)y + md.offset, ld, s, e);
+        ++mi;
+      }
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+    double acc[AIM_NSTAGE] = {0};
+    for (size_t g = 0; g < (size_t)nrep * nm; ++g)
+      for (int i = 0; i < AIM_NSTAGE; ++i) {
+        float ms = 0;
+        HIPCHECK(hipEventElapsedTime(&ms, ev[g * (AIM_NSTAGE + 1) + i], ev[g * (AIM_NSTAGE + 1) + i + 1]));
+        acc[i] += ms;
+      }
+    if (stage_ms)
+      for (int i = 0; i < AIM_NSTAGE; ++i) stage_ms[i] = acc[i];
+    if (total_ms) {
+      float ms = 0;
+      HIPCHECK(hipEventElapsedTime(&ms, ev.front(), ev.back()));
+      *total_ms = ms;
     }
   });
+  for (auto &e : ev)
+    if (e) (void)hipEventDestroy(e);
+  return r;
 }
 
 aim_status aim_excitation(aim_plan *plan, int32_t nwaves, const aim_planewave *waves, void *b,
@@ -314,27 +378,20 @@ aim_status aim_debug_far_stage(aim_plan *plan, aim_precision prec, int32_t mesh,
   if (!plan || !x || !grid_out || mesh < 0 || mesh >= plan->nmesh || nrhs < 1 || stage < 1 ||
       stage > 6)
     return fail(AIM_ERR_ARG, "bad argument");
+  if (prec != AIM_FP64 && prec != AIM_MIXED) return fail(AIM_ERR_ARG, "bad precision");
   if (prec == AIM_MIXED && !plan->mixed) return fail(AIM_ERR_STATE, "plan has no FP32 data");
   hipStream_t s = (hipStream_t)hip_stream;
   return guarded([&] {
     MeshDev &md = plan->mesh[mesh];
-    const HostPlan &h = md.hp;
-    const int64_t F = 4 * (int64_t)nrhs;
-    const int64_t V0 = (int64_t)h.grid[0] * h.grid[1] * h.grid[2];
-    const int64_t V1 = (int64_t)h.grid[0] * h.grid[1] * h.pad[2];
-    const int64_t V2 = (int64_t)h.grid[0] * h.pad[1] * h.pad[2];
-    const int64_t sizes[7] = {0, V0, V1, V2, V2, V1, V0};
-    const int which[7] = {0, 0, 1, 2, 2, 1, 0};
-    const int pidx = prec == AIM_FP64 ? 0 : 1;
-    const size_t es = prec == AIM_FP64 ? sizeof(double2) : sizeof(float2);
-    if (prec == AIM_FP64)
+    if (prec == AIM_FP64) {
       far_stages<double, double>(plan, md, nrhs, (const double2 *)x + md.offset, plan->n_total,
                                  stage, s);
-    else
+      copy_far_stage<double>(plan, md, nrhs, stage, grid_out, s);
+    } else {
       far_stages<float, float>(plan, md, nrhs, (const float2 *)x + md.offset, plan->n_total, stage,
                                s);
-    HIPCHECK(hipMemcpyAsync(grid_out, plan->work[pidx][which[stage]], es * F * sizes[stage],
-                            hipMemcpyDeviceToDevice, s));
+      copy_far_stage<float>(plan, md, nrhs, stage, grid_out, s);
+    }
   });
 }
 

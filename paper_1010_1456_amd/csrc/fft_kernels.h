@@ -24,6 +24,7 @@
 
 #include "aim_internal.h"
 #include "fft_core.h"
+#include "fft_map.h"
 #include "fft_plans.h"
 
 namespace aim {
@@ -31,6 +32,7 @@ namespace fftk {
 using namespace fftc;
 
 constexpr int kLdsBudget = 48 * 1024;
+
 
 template <int R0, int R1, int R2>
 struct PlanC {
@@ -121,8 +123,8 @@ __global__ void __launch_bounds__((threads_contig<T, PC>()))
 template <typename T, bool INV, class PC>
 __global__ void __launch_bounds__((threads_strided<T, PC>()))
     k_fft_strided(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, int n_in, int n_out,
-                  int64_t inner, int ntile, int64_t in_elem, int64_t in_outer, int64_t out_elem,
-                  int64_t out_outer, const cx<T> *__restrict__ tw, int B) {
+                  int64_t inner, int ntile, LineMap imap, LineMap omap,
+                  const cx<T> *__restrict__ tw, int B) {
   using V = cx<T>;
   extern __shared__ unsigned char smem_raw[];
   V *lds = reinterpret_cast<V *>(smem_raw);
@@ -132,8 +134,9 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
   const int b = threadIdx.x % B;
   const int beta = threadIdx.x / B;
   const bool line_ok = (c0 + b < inner);
-  const V *gin = in + o * in_outer + c0 + b;
-  V *gout = out + o * out_outer + c0 + b;
+  const V *gin = in + line_base(imap, o, c0 + b);
+  V *gout = out + line_base(omap, o, c0 + b);
+  const int64_t in_elem = line_elem(imap), out_elem = line_elem(omap);
   static_for<PC::ns>([&](auto s_) AIM_AI {
     constexpr int s = decltype(s_)::value;
     constexpr int R = PC::r(s), L = PC::lb(s), Mp = P / (L * R), nb = P / R;
@@ -158,18 +161,29 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
   });
 }
 
-// x pass over data [nfield][n_x][Py][Pz]: lines (ky, kz), tile over kz; the
-// work-group loops over the fields so the spectrum values stay in cache.
+// x pass over data in the kz-blocked layout [nfield][Pz/blk][n_x][Py][blk]
+// (blk == 0: plain [nfield][n_x][Py][Pz]): lines (ky, kz), tile over kz. One
+// work-group per (tile, field). Work-groups are dealt round-robin to the 8
+// XCDs, so block ids are arranged for the fields of one tile to land on the
+// same XCD back to back and share its L2 copy of the spectrum tile.
+constexpr int kXcd = 8;
+
 template <typename T, class PC>
 __global__ void __launch_bounds__((threads_strided<T, PC>()))
     k_fft_mid(cx<T> *__restrict__ data, int n_x, int nfield, int Py, int Pz, int ntile, int Hy,
-              int Hz, const cx<T> *__restrict__ ghat, const cx<T> *__restrict__ tw, int B) {
+              int Hz, const cx<T> *__restrict__ ghat, const cx<T> *__restrict__ tw, int B, int blk,
+              int64_t fstride) {
   using V = cx<T>;
   extern __shared__ unsigned char smem_raw[];
   V *lds = reinterpret_cast<V *>(smem_raw);
   constexpr int P = PC::P, ns = PC::ns;
-  const int ky = blockIdx.x / ntile;
-  const int kz0 = (blockIdx.x % ntile) * B;
+  const int xcd = blockIdx.x % kXcd;
+  const int jb = blockIdx.x / kXcd;
+  const int field = jb % nfield;
+  const int tile = (jb / nfield) * kXcd + xcd;
+  if (tile >= Py * ntile) return;  // padding blocks: exit before any barrier
+  const int ky = tile / ntile;
+  const int kz0 = (tile % ntile) * B;
   const int b = threadIdx.x % B;
   const int beta = threadIdx.x / B;
   const int kz = kz0 + b;
@@ -178,12 +192,12 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
   const int fkz = (kz <= Pz - kz) ? kz : Pz - kz;
   const int64_t gofs = (int64_t)fky * Hz + fkz;
   const int64_t gplane = (int64_t)Hy * Hz;
-  const int64_t es = (int64_t)Py * Pz;
-  const int64_t fstride = (int64_t)n_x * es;
+  const int64_t es = blk == 0 ? (int64_t)Py * Pz : (int64_t)Py * blk;  // x stride
+  const int64_t lofs = blk == 0 ? (int64_t)ky * Pz + kz
+                                : (int64_t)(kz / blk) * n_x * es + (int64_t)ky * blk + kz % blk;
 
-  for (int f = 0; f < nfield; ++f) {
-    V *line = data + f * fstride + (int64_t)ky * Pz + kz;
-    if (f > 0) __syncthreads();  // LDS reuse across fields
+  {
+    V *line = data + field * fstride + lofs;
     // forward stages except the last
     static_for<ns - 1>([&](auto s_) AIM_AI {
       constexpr int s = decltype(s_)::value;
@@ -288,8 +302,8 @@ void launch_contig(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t lin
 
 template <typename T, class PC>
 void launch_strided(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t outer, int64_t inner,
-                    int64_t in_elem, int64_t in_outer, int64_t out_elem, int64_t out_outer,
-                    bool inverse, const cx<T> *tw, hipStream_t s) {
+                    const LineMap &imap, const LineMap &omap, bool inverse, const cx<T> *tw,
+                    hipStream_t s) {
   constexpr int B = tile_strided<T, PC>();
   constexpr int threads = threads_strided<T, PC>();
   const int ntile = (int)((inner + B - 1) / B);
@@ -297,25 +311,24 @@ void launch_strided(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t ou
   const int64_t blocks = outer * ntile;
   if (inverse)
     hipLaunchKernelGGL((k_fft_strided<T, true, PC>), dim3((unsigned)blocks), dim3(threads), lds, s,
-                       in, out, n_in, n_out, inner, ntile, in_elem, in_outer, out_elem, out_outer,
-                       tw, B);
+                       in, out, n_in, n_out, inner, ntile, imap, omap, tw, B);
   else
     hipLaunchKernelGGL((k_fft_strided<T, false, PC>), dim3((unsigned)blocks), dim3(threads), lds, s,
-                       in, out, n_in, n_out, inner, ntile, in_elem, in_outer, out_elem, out_outer,
-                       tw, B);
+                       in, out, n_in, n_out, inner, ntile, imap, omap, tw, B);
   LAUNCHCHECK();
 }
 
 template <typename T, class PC>
 void launch_mid(cx<T> *data, int n_x, int nfield, int Py, int Pz, int Hy, int Hz,
-                const cx<T> *ghat, const cx<T> *tw, hipStream_t s) {
+                const cx<T> *ghat, const cx<T> *tw, int blk, int64_t fstride, hipStream_t s) {
   constexpr int B = tile_strided<T, PC>();
   constexpr int threads = threads_strided<T, PC>();
   const int ntile = (Pz + B - 1) / B;
   const size_t lds = PC::ns > 1 ? (size_t)PC::P * B * sizeof(cx<T>) : 0;
-  const int64_t blocks = (int64_t)Py * ntile;
+  const int64_t tiles = ((int64_t)Py * ntile + kXcd - 1) / kXcd * kXcd;
+  const int64_t blocks = tiles * nfield;
   hipLaunchKernelGGL((k_fft_mid<T, PC>), dim3((unsigned)blocks), dim3(threads), lds, s, data, n_x,
-                     nfield, Py, Pz, ntile, Hy, Hz, ghat, tw, B);
+                     nfield, Py, Pz, ntile, Hy, Hz, ghat, tw, B, blk, fstride);
   LAUNCHCHECK();
 }
 

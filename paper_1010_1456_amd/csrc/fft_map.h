@@ -1,0 +1,56 @@
+// Line addressing of the strided FFT passes (shared by the passes and their
+// callers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace aim {
+namespace fftk {
+
+// Address of element i of line (o, c) of a strided pass, with o the outer
+// line index and c the contiguous line index. With o = o_hi * lo_count + o_lo:
+//   plain   (blk == 0): o_hi*hi + o_lo*lo + c            + i*elem
+//   blocked (blk  > 0): o_hi*hi + o_lo*lo + (c/blk)*bstr + c%blk + i*blk
+// The blocked form stores the contiguous index in runs of blk (128 bytes), so
+// the lines of one work-group lie close together in memory.
+struct LineMap {
+  int64_t hi, lo, bstr, elem;
+  int lo_count, blk;
+};
+__host__ __device__ inline int64_t line_base(const LineMap &m, int64_t o, int64_t c) {
+  const int64_t oh = o / m.lo_count, ol = o - oh * m.lo_count;
+  const int64_t b = oh * m.hi + ol * m.lo;
+  if (m.blk == 0) return b + c;
+  return b + (c / m.blk) * m.bstr + c % m.blk;
+}
+__host__ __device__ inline int64_t line_elem(const LineMap &m) { return m.blk == 0 ? m.elem : m.blk; }
+
+// plain line map: line (o, c) starts at o * outer + c, elements elem apart
+inline LineMap plain_map(int64_t outer, int64_t elem) {
+  LineMap m{};
+  m.hi = outer;
+  m.lo = 0;
+  m.bstr = 0;
+  m.elem = elem;
+  m.lo_count = 1;
+  m.blk = 0;
+  return m;
+}
+
+// kz-blocked grid [F][ceil(Pz/blk)][Nx][Py][blk] seen by the y passes: outer
+// o = f * Nx + x, contiguous index kz, element ky
+inline LineMap blocked_map(int64_t field_stride, int Nx, int Py, int blk) {
+  LineMap m{};
+  m.hi = field_stride;
+  m.lo = (int64_t)Py * blk;
+  m.bstr = (int64_t)Nx * Py * blk;
+  m.elem = 0;
+  m.lo_count = Nx;
+  m.blk = blk;
+  return m;
+}
+
+}  // namespace fftk
+}  // namespace aim

@@ -10,42 +10,71 @@
 #include <algorithm>
 
 #include "aim_internal.h"
+#include "fft_map.h"
 
 namespace aim {
 
 namespace {
 
-template <typename T>
-__device__ __forceinline__ void atomic_add_real(T *p, T v) {
-  unsafeAtomicAdd(p, v);
-}
-
-// s_q[node(n, u)] += Lambda[n][q][u] x_n for every basis n, stencil node u,
-// component q, right-hand side r. One thread per (n, u).
+// Gather form: grid node v sums Lambda_T[e] x_{col[e]} over its entries, so
+// every node (also empty ones) is written exactly once and no atomics or
+// clearing pass are needed. One thread per node, in grid order.
 template <typename T, typename TX>
 __global__ void __launch_bounds__(256)
-    k_anterp(const cx<TX> *__restrict__ x, int64_t ldx, int nrhs, const T *__restrict__ lam,
-             const int32_t *__restrict__ anchor_lin, const int32_t *__restrict__ soff, int64_t n,
-             int K, cx<T> *__restrict__ grid, int64_t V0) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * K) return;
-  const int64_t b = t / K;
-  const int u = (int)(t - b * K);
-  const int64_t node = (int64_t)anchor_lin[b] + soff[u];
-  T w[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) w[q] = lam[(b * 4 + q) * K + u];
+    k_anterp_gather(const cx<TX> *__restrict__ x, int64_t ldx, int nrhs,
+                    const int32_t *__restrict__ node_ptr, const int32_t *__restrict__ ent_col,
+                    const T *__restrict__ lamT, cx<T> *__restrict__ grid, int64_t V0) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V0) return;
+  const int e0 = node_ptr[v], e1 = node_ptr[v + 1];
   for (int r = 0; r < nrhs; ++r) {
-    const cx<TX> xv = x[(int64_t)r * ldx + b];
-    const T xr = (T)xv.x, xi = (T)xv.y;
+    const cx<TX> *xr = x + (int64_t)r * ldx;
+    T a[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    // entries in groups of 4 so that their independent loads overlap
+    for (int e = e0; e < e1; e += 4) {
+      int c[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) c[k] = (e + k < e1) ? ent_col[e + k] : -1;
+      cx<TX> xv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        xv[k].x = 0;
+        xv[k].y = 0;
+        if (c[k] >= 0) xv[k] = xr[c[k]];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (c[k] < 0) break;
+        const T xa = (T)xv[k].x, xb = (T)xv[k].y;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const T w = lamT[(int64_t)(e + k) * 4 + q];
+          a[q][0] += w * xa;
+          a[q][1] += w * xb;
+        }
+      }
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      if (w[q] == (T)0) continue;
-      T *g = reinterpret_cast<T *>(grid + ((int64_t)(r * 4 + q)) * V0 + node);
-      atomic_add_real(g, w[q] * xr);
-      atomic_add_real(g + 1, w[q] * xi);
+      cx<T> o;
+      o.x = a[q][0];
+      o.y = a[q][1];
+      grid[((int64_t)(r * 4 + q)) * V0 + v] = o;
     }
   }
+}
+
+template <typename T>
+__global__ void k_unblock(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, int64_t F, int Nx,
+                          int Py, int Pz, int blk, int64_t fstride) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = F * Nx * Py * Pz;
+  if (t >= tot) return;
+  const int kz = (int)(t % Pz);
+  const int ky = (int)((t / Pz) % Py);
+  const int x = (int)((t / ((int64_t)Py * Pz)) % Nx);
+  const int64_t f = t / ((int64_t)Nx * Py * Pz);
+  out[t] = in[f * fstride + ((int64_t)(kz / blk) * Nx + x) * Py * blk + (int64_t)ky * blk + kz % blk];
 }
 
 template <typename V>
@@ -121,6 +150,16 @@ const float *lam_of<float>(const MeshDev &md) {
   return md.lam32;
 }
 template <typename T>
+const T *lamT_of(const MeshDev &md);
+template <>
+const double *lamT_of<double>(const MeshDev &md) {
+  return md.lamT64;
+}
+template <>
+const float *lamT_of<float>(const MeshDev &md) {
+  return md.lamT32;
+}
+template <typename T>
 const cx<T> *near_of(const MeshDev &md);
 template <>
 const double2 *near_of<double>(const MeshDev &md) {
@@ -166,7 +205,10 @@ void *work_buffer(Plan *pl, int prec, int which, size_t bytes) {
 
 template <typename T, typename TX>
 void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, int stop,
-                hipStream_t s) {
+                hipStream_t s, hipEvent_t *ev) {
+  auto mark = [&](int i) {
+    if (ev) HIPCHECK(hipEventRecord(ev[i], s));
+  };
   const HostPlan &h = md.hp;
   const int prec = sizeof(T) == 8 ? 0 : 1;
   const int Nx = h.grid[0], Ny = h.grid[1], Nz = h.grid[2];
@@ -175,39 +217,42 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
   const int64_t F = 4 * (int64_t)nrhs;
   const int64_t V0 = (int64_t)Nx * Ny * Nz;
   const int64_t V1 = (int64_t)Nx * Ny * Pz;
-  const int64_t V2 = (int64_t)Nx * Py * Pz;
+  const int blk = kGridBlock<T>;
+  const int64_t V2 = (int64_t)Nx * Py * ((Pz + blk - 1) / blk * blk);  // kz-blocked
   cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * V0);
   cx<T> *g1 = (cx<T> *)work_buffer(pl, prec, 1, sizeof(cx<T>) * F * V1);
   cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2);
-  const int K = h.K;
-  HIPCHECK(hipMemsetAsync(g0, 0, sizeof(cx<T>) * F * V0, s));
-  {
-    const int64_t threads = h.n * K;
-    hipLaunchKernelGGL((k_anterp<T, TX>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
-                       x, ldx, nrhs, lam_of<T>(md), md.anchor_lin, md.stencil_off, h.n, K, g0, V0);
-    LAUNCHCHECK();
-  }
+  const fftk::LineMap m1 = fftk::plain_map((int64_t)Ny * Pz, Pz);
+  const fftk::LineMap m2 = fftk::blocked_map(V2, Nx, Py, blk);
+  mark(0);
+  hipLaunchKernelGGL((k_anterp_gather<T, TX>), dim3((unsigned)((V0 + 255) / 256)), dim3(256), 0, s,
+                     x, ldx, nrhs, md.node_ptr, md.ent_col, lamT_of<T>(md), g0, V0);
+  LAUNCHCHECK();
+  mark(1);
   if (stop <= 1) return;
   fft_pass_contig(g0, g1, md.plan[2], Nz, Pz, F * Nx * Ny, Nz, Pz, false, tw_of<T>(md, 2), s);
+  mark(2);
   if (stop <= 2) return;
-  fft_pass_strided(g1, g2, md.plan[1], Ny, Py, F * Nx, Pz, Pz, (int64_t)Ny * Pz, Pz,
-                      (int64_t)Py * Pz, false, tw_of<T>(md, 1), s);
+  fft_pass_strided(g1, g2, md.plan[1], Ny, Py, F * Nx, Pz, m1, m2, false, tw_of<T>(md, 1), s);
+  mark(3);
   if (stop <= 3) return;
   fft_mid_pass(g2, md.plan[0], Nx, (int)F, Py, Pz, md.H[0], md.H[1], md.H[2], ghat_of<T>(md),
-                  tw_of<T>(md, 0), s);
+               tw_of<T>(md, 0), blk, V2, s);
+  mark(4);
   if (stop <= 4) return;
-  fft_pass_strided(g2, g1, md.plan[1], Py, Ny, F * Nx, Pz, Pz, (int64_t)Py * Pz, Pz,
-                      (int64_t)Ny * Pz, true, tw_of<T>(md, 1), s);
+  fft_pass_strided(g2, g1, md.plan[1], Py, Ny, F * Nx, Pz, m2, m1, true, tw_of<T>(md, 1), s);
+  mark(5);
   if (stop <= 5) return;
   fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * Nx * Ny, Pz, Nz, true, tw_of<T>(md, 2), s);
+  mark(6);
 }
 
 template <typename T, typename TX, typename TY>
 void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, cx<TY> *y,
-                 int64_t ldy, hipStream_t s) {
+                 int64_t ldy, hipStream_t s, hipEvent_t *ev) {
   const HostPlan &h = md.hp;
   const int prec = sizeof(T) == 8 ? 0 : 1;
-  far_stages<T, TX>(pl, md, nrhs, x, ldx, 6, s);
+  far_stages<T, TX>(pl, md, nrhs, x, ldx, 6, s, ev);
   const cx<T> *phi = (const cx<T> *)pl->work[prec][0];
   const int64_t V0 = (int64_t)h.grid[0] * h.grid[1] * h.grid[2];
   const int rows_per_block = 4;
@@ -217,19 +262,44 @@ void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, 
                      md.rowptr, md.cols, near_of<T>(md), x, ldx, y, ldy, h.n,
                      (T)(h.k * kEta0), (T)(1.0 / (h.k * h.k)));
   LAUNCHCHECK();
+  if (ev) HIPCHECK(hipEventRecord(ev[7], s));
 }
 
+template <typename T>
+void copy_far_stage(Plan *pl, MeshDev &md, int nrhs, int stage, void *out, hipStream_t s) {
+  const HostPlan &h = md.hp;
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  const int Nx = h.grid[0], Ny = h.grid[1], Nz = h.grid[2];
+  const int Py = h.pad[1], Pz = h.pad[2];
+  const int64_t F = 4 * (int64_t)nrhs;
+  const int blk = kGridBlock<T>;
+  const int64_t V2 = (int64_t)Nx * Py * ((Pz + blk - 1) / blk * blk);
+  if (stage == 3 || stage == 4) {
+    const int64_t tot = F * Nx * Py * Pz;
+    hipLaunchKernelGGL((k_unblock<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                       (const cx<T> *)pl->work[prec][2], (cx<T> *)out, F, Nx, Py, Pz, blk, V2);
+    LAUNCHCHECK();
+    return;
+  }
+  const int64_t sz = (stage == 2 || stage == 5) ? (int64_t)Nx * Ny * Pz : (int64_t)Nx * Ny * Nz;
+  const int which = (stage == 2 || stage == 5) ? 1 : 0;
+  HIPCHECK(hipMemcpyAsync(out, pl->work[prec][which], sizeof(cx<T>) * F * sz,
+                          hipMemcpyDeviceToDevice, s));
+}
+template void copy_far_stage<double>(Plan *, MeshDev &, int, int, void *, hipStream_t);
+template void copy_far_stage<float>(Plan *, MeshDev &, int, int, void *, hipStream_t);
+
 template void far_stages<double, double>(Plan *, MeshDev &, int, const double2 *, int64_t, int,
-                                         hipStream_t);
+                                         hipStream_t, hipEvent_t *);
 template void far_stages<float, float>(Plan *, MeshDev &, int, const float2 *, int64_t, int,
-                                       hipStream_t);
+                                       hipStream_t, hipEvent_t *);
 template void far_stages<float, double>(Plan *, MeshDev &, int, const double2 *, int64_t, int,
-                                        hipStream_t);
+                                        hipStream_t, hipEvent_t *);
 template void matvec_mesh<double, double, double>(Plan *, MeshDev &, int, const double2 *, int64_t,
-                                                  double2 *, int64_t, hipStream_t);
+                                                  double2 *, int64_t, hipStream_t, hipEvent_t *);
 template void matvec_mesh<float, float, float>(Plan *, MeshDev &, int, const float2 *, int64_t,
-                                               float2 *, int64_t, hipStream_t);
+                                               float2 *, int64_t, hipStream_t, hipEvent_t *);
 template void matvec_mesh<float, double, double>(Plan *, MeshDev &, int, const double2 *, int64_t,
-                                                 double2 *, int64_t, hipStream_t);
+                                                 double2 *, int64_t, hipStream_t, hipEvent_t *);
 
 }  // namespace aim

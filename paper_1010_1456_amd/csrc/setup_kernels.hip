@@ -5,6 +5,7 @@
 #include <cstring>
 
 #include "aim_internal.h"
+#include "fft_map.h"
 #include "geom_device.h"
 
 namespace aim {
@@ -63,6 +64,32 @@ __global__ void k_projection(const int32_t *rwg, const double *len, const double
     }
   }
   for (int q = 0; q < 4; ++q) lam[(b * 4 + q) * K + u] = acc[q];
+}
+
+// 1 where a (basis, stencil node) pair has any non-zero weight
+__global__ void k_lam_mask(const double *lam, int64_t n, int K, uint8_t *mask) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * K) return;
+  const int64_t b = t / K;
+  const int u = (int)(t - b * K);
+  bool nz = false;
+  for (int q = 0; q < 4; ++q) nz |= lam[(b * 4 + q) * K + u] != 0.0;
+  mask[t] = nz ? 1 : 0;
+}
+
+// lamT[e][q] = Lambda[src / K][q][src % K] for entry e with src = ent_src[e]
+__global__ void k_lam_transpose(const double *lam, const int32_t *ent_src, int64_t ne, int K,
+                                double *lamT64, float *lamT32) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const int64_t src = ent_src[e];
+  const int64_t b = src / K;
+  const int u = (int)(src - b * K);
+  for (int q = 0; q < 4; ++q) {
+    const double v = lam[(b * 4 + q) * K + u];
+    lamT64[e * 4 + q] = v;
+    if (lamT32) lamT32[e * 4 + q] = (float)v;
+  }
 }
 
 __global__ void k_to_float(const double *in, float *out, int64_t n) {
@@ -292,6 +319,46 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
     LAUNCHCHECK();
   }
 
+  // node-ordered (transposed) projection for the gather form of anterpolation
+  {
+    const int64_t NK = n * K;
+    uint8_t *dmask = (uint8_t *)dev_alloc(pl, NK);
+    hipLaunchKernelGGL(k_lam_mask, dim3(blocks_for(NK, 256)), dim3(256), 0, s, md.lam64, n, K, dmask);
+    LAUNCHCHECK();
+    std::vector<uint8_t> mask(NK);
+    HIPCHECK(hipMemcpyAsync(mask.data(), dmask, NK, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    dev_free(pl, dmask);
+    const int64_t V0 = (int64_t)h.grid[0] * h.grid[1] * h.grid[2];
+    std::vector<int32_t> ptr(V0 + 1, 0);
+    for (int64_t b = 0; b < n; ++b)
+      for (int u = 0; u < K; ++u)
+        if (mask[b * K + u]) ptr[alin[b] + soff[u] + 1]++;
+    for (int64_t v = 0; v < V0; ++v) ptr[v + 1] += ptr[v];
+    const int64_t ne = ptr[V0];
+    if (ne > INT32_MAX) throw Error(AIM_ERR_ARG, "projection too large for 32-bit indexing");
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1), col(std::max<int64_t>(ne, 1)),
+        src(std::max<int64_t>(ne, 1));
+    for (int64_t b = 0; b < n; ++b)  // entries of a node in (basis, node) order
+      for (int u = 0; u < K; ++u)
+        if (mask[b * K + u]) {
+          const int32_t e = fill[alin[b] + soff[u]]++;
+          col[e] = (int32_t)b;
+          src[e] = (int32_t)(b * K + u);
+        }
+    md.n_entries = ne;
+    md.node_ptr = upload(pl, ptr.data(), ptr.size(), s);
+    md.ent_col = upload(pl, col.data(), col.size(), s);
+    int32_t *dsrc = upload(pl, src.data(), src.size(), s);
+    md.lamT64 = (double *)dev_alloc(pl, sizeof(double) * 4 * std::max<int64_t>(ne, 1));
+    if (pl->mixed) md.lamT32 = (float *)dev_alloc(pl, sizeof(float) * 4 * std::max<int64_t>(ne, 1));
+    hipLaunchKernelGGL(k_lam_transpose, dim3(blocks_for(std::max<int64_t>(ne, 1), 256)), dim3(256), 0,
+                       s, md.lam64, dsrc, ne, K, md.lamT64, md.lamT32);
+    LAUNCHCHECK();
+    HIPCHECK(hipStreamSynchronize(s));
+    dev_free(pl, dsrc);
+  }
+
   // FFT plans, twiddles, Green's spectrum octant
   for (int d = 0; d < 3; ++d) {
     if (!fft_plan_for(h.pad[d], &md.plan[d])) throw Error(AIM_ERR_ARG, "unsupported FFT length");
@@ -307,10 +374,10 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
                        h.grid[0], h.grid[1], h.grid[2], h.k, h.h);
     LAUNCHCHECK();
     fft_pass_contig(e0, e1, md.plan[2], Pz, Pz, (int64_t)Px * Py, Pz, Pz, false, md.tw64[2], s);
-    fft_pass_strided(e1, e0, md.plan[1], Py, Py, Px, Pz, Pz, (int64_t)Py * Pz, Pz,
-                             (int64_t)Py * Pz, false, md.tw64[1], s);
-    fft_pass_strided(e0, e1, md.plan[0], Px, Px, 1, (int64_t)Py * Pz, (int64_t)Py * Pz, 0,
-                             (int64_t)Py * Pz, 0, false, md.tw64[0], s);
+    const fftk::LineMap my = fftk::plain_map((int64_t)Py * Pz, Pz);
+    const fftk::LineMap mx = fftk::plain_map(0, (int64_t)Py * Pz);
+    fft_pass_strided(e1, e0, md.plan[1], Py, Py, Px, Pz, my, my, false, md.tw64[1], s);
+    fft_pass_strided(e0, e1, md.plan[0], Px, Px, 1, (int64_t)Py * Pz, mx, mx, false, md.tw64[0], s);
     const int64_t noct = (int64_t)md.H[0] * md.H[1] * md.H[2];
     md.ghat64 = (double2 *)dev_alloc(pl, sizeof(double2) * noct);
     hipLaunchKernelGGL(k_extract_octant, dim3(blocks_for(noct, 256)), dim3(256), 0, s, e1,
