@@ -124,6 +124,9 @@ def main(argv=None):
     ap.add_argument("--workload", default="sphere8", choices=["sphere8", "plate16", "plate1", "plate128"])
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="first run a plain elementwise copy of 256 MiB (3 launches) whose "
+                         "FETCH_SIZE/WRITE_SIZE counters calibrate the HBM byte counts")
     args = ap.parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -136,6 +139,13 @@ def main(argv=None):
     from paper_1010_1456_amd import aim as A
     from workloads import CONFIGS, config_mesh, random_current
 
+    if args.calibrate:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)  # reads 256 MiB, writes 256 MiB
+        torch.cuda.synchronize()
+        del a, b
     cfg = CONFIGS[args.workload]
     log(f"[bench] meshing {args.workload}")
     mesh = config_mesh(args.workload)

@@ -92,6 +92,11 @@ __global__ void __launch_bounds__((threads_contig<T, PC>()))
   V *lds = reinterpret_cast<V *>(smem_raw);
   constexpr int P = PC::P, LS = P + 1;
   const int64_t line0 = (int64_t)blockIdx.x * B;
+  V *twl = lds + (PC::ns > 1 ? B * LS : 0);  // twiddle table in LDS
+  if constexpr (PC::ns > 1) {
+    for (int i = threadIdx.x; i < P; i += blockDim.x) twl[i] = tw[i];
+    __syncthreads();
+  }
   static_for<PC::ns>([&](auto s_) AIM_AI {
     constexpr int s = decltype(s_)::value;
     constexpr int R = PC::r(s), L = PC::lb(s), Mp = P / (L * R), nb = P / R;
@@ -101,6 +106,7 @@ __global__ void __launch_bounds__((threads_contig<T, PC>()))
     const V *gin = in + (line0 + b) * in_ls;
     V *gout = out + (line0 + b) * out_ls;
     V *ll = lds + b * LS;
+    (void)tw;
     auto ld = [&](int i) AIM_AI -> V {
       if constexpr (first) return (i < n_in) ? gin[i] : mk<V>((T)0, (T)0);
       else return ll[i];
@@ -115,7 +121,7 @@ __global__ void __launch_bounds__((threads_contig<T, PC>()))
     V v[R];
     if (active) stage_load<R, INV, V>(v, beta, Mp, ld);
     if constexpr (!first && !last) __syncthreads();
-    if (active) stage_compute_store<R, INV, V>(v, beta, L, Mp, tw, st);
+    if (active) stage_compute_store<R, INV, V>(v, beta, L, Mp, twl, st);
     if constexpr (!last) __syncthreads();
   });
 }
@@ -124,11 +130,12 @@ template <typename T, bool INV, class PC>
 __global__ void __launch_bounds__((threads_strided<T, PC>()))
     k_fft_strided(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, int n_in, int n_out,
                   int64_t inner, int ntile, LineMap imap, LineMap omap,
-                  const cx<T> *__restrict__ tw, int B) {
+                  const cx<T> *__restrict__ tw, int) {
   using V = cx<T>;
   extern __shared__ unsigned char smem_raw[];
   V *lds = reinterpret_cast<V *>(smem_raw);
   constexpr int P = PC::P;
+  constexpr int B = tile_strided<T, PC>();
   const int64_t o = blockIdx.x / ntile;
   const int64_t c0 = (int64_t)(blockIdx.x % ntile) * B;
   const int b = threadIdx.x % B;
@@ -136,19 +143,29 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
   const bool line_ok = (c0 + b < inner);
   const V *gin = in + line_base(imap, o, c0 + b);
   V *gout = out + line_base(omap, o, c0 + b);
-  const int64_t in_elem = line_elem(imap), out_elem = line_elem(omap);
+  // element offsets within a line fit in 32 bits (checked by the planner);
+  // the first stage reads elements beta + q M' and the last writes
+  // beta + p L, so address them from beta's element
+  const int in_elem = (int)line_elem(imap), out_elem = (int)line_elem(omap);
+  const V *gin_b = gin + beta * in_elem;
+  V *gout_b = gout + beta * out_elem;
+  V *twl = lds + (PC::ns > 1 ? P * B : 0);
+  if constexpr (PC::ns > 1) {
+    for (int i = threadIdx.x; i < P; i += blockDim.x) twl[i] = tw[i];
+    __syncthreads();
+  }
   static_for<PC::ns>([&](auto s_) AIM_AI {
     constexpr int s = decltype(s_)::value;
     constexpr int R = PC::r(s), L = PC::lb(s), Mp = P / (L * R), nb = P / R;
     constexpr bool first = (s == 0), last = (s == PC::ns - 1);
     const bool active = line_ok && (beta < nb);
     auto ld = [&](int i) AIM_AI -> V {
-      if constexpr (first) return (i < n_in) ? gin[(int64_t)i * in_elem] : mk<V>((T)0, (T)0);
+      if constexpr (first) return (i < n_in) ? gin_b[(i - beta) * in_elem] : mk<V>((T)0, (T)0);
       else return lds[i * B + b];
     };
     auto st = [&](int i, V v) AIM_AI {
       if constexpr (last) {
-        if (i < n_out) gout[(int64_t)i * out_elem] = v;
+        if (i < n_out) gout_b[(i - beta) * out_elem] = v;
       } else {
         lds[i * B + b] = v;
       }
@@ -156,7 +173,7 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
     V v[R];
     if (active) stage_load<R, INV, V>(v, beta, Mp, ld);
     if constexpr (!first && !last) __syncthreads();
-    if (active) stage_compute_store<R, INV, V>(v, beta, L, Mp, tw, st);
+    if (active) stage_compute_store<R, INV, V>(v, beta, L, Mp, twl, st);
     if constexpr (!last) __syncthreads();
   });
 }
@@ -171,12 +188,13 @@ constexpr int kXcd = 8;
 template <typename T, class PC>
 __global__ void __launch_bounds__((threads_strided<T, PC>()))
     k_fft_mid(cx<T> *__restrict__ data, int n_x, int nfield, int Py, int Pz, int ntile, int Hy,
-              int Hz, const cx<T> *__restrict__ ghat, const cx<T> *__restrict__ tw, int B, int blk,
+              int Hz, const cx<T> *__restrict__ ghat, const cx<T> *__restrict__ tw, int, int blk,
               int64_t fstride) {
   using V = cx<T>;
   extern __shared__ unsigned char smem_raw[];
   V *lds = reinterpret_cast<V *>(smem_raw);
   constexpr int P = PC::P, ns = PC::ns;
+  constexpr int B = tile_strided<T, PC>();
   const int xcd = blockIdx.x % kXcd;
   const int jb = blockIdx.x / kXcd;
   const int field = jb % nfield;
@@ -190,14 +208,18 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
   const bool line_ok = kz < Pz;
   const int fky = (ky <= Py - ky) ? ky : Py - ky;
   const int fkz = (kz <= Pz - kz) ? kz : Pz - kz;
-  const int64_t gofs = (int64_t)fky * Hz + fkz;
-  const int64_t gplane = (int64_t)Hy * Hz;
-  const int64_t es = blk == 0 ? (int64_t)Py * Pz : (int64_t)Py * blk;  // x stride
+  const int gofs = fky * Hz + fkz;  // octant offsets fit in 32 bits
+  const int gplane = Hy * Hz;
+  const int es = blk == 0 ? Py * Pz : Py * blk;  // x stride (32-bit, checked by the planner)
+  V *twl = lds + (ns > 1 ? P * B : 0);
+  for (int i = threadIdx.x; i < P; i += blockDim.x) twl[i] = tw[i];
+  __syncthreads();
   const int64_t lofs = blk == 0 ? (int64_t)ky * Pz + kz
                                 : (int64_t)(kz / blk) * n_x * es + (int64_t)ky * blk + kz % blk;
 
   {
     V *line = data + field * fstride + lofs;
+    V *line_b = line + beta * es;  // element beta of the line
     // forward stages except the last
     static_for<ns - 1>([&](auto s_) AIM_AI {
       constexpr int s = decltype(s_)::value;
@@ -205,14 +227,14 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
       constexpr bool first = (s == 0);
       const bool active = line_ok && (beta < nb);
       auto ld = [&](int i) AIM_AI -> V {
-        if constexpr (first) return (i < n_x) ? line[(int64_t)i * es] : mk<V>((T)0, (T)0);
+        if constexpr (first) return (i < n_x) ? line_b[(i - beta) * es] : mk<V>((T)0, (T)0);
         else return lds[i * B + b];
       };
       auto st = [&](int i, V v) AIM_AI { lds[i * B + b] = v; };
       V v[R];
       if (active) stage_load<R, false, V>(v, beta, Mp, ld);
       if constexpr (!first) __syncthreads();
-      if (active) stage_compute_store<R, false, V>(v, beta, L, Mp, tw, st);
+      if (active) stage_compute_store<R, false, V>(v, beta, L, Mp, twl, st);
       __syncthreads();
     });
     // last forward stage, spectrum multiply, first inverse stage in registers
@@ -227,7 +249,7 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
         static_for<R>([&](auto q_) AIM_AI {
           constexpr int q = decltype(q_)::value;
           const int i = j * R + q;
-          if constexpr (single) v[q] = (i < n_x) ? line[(int64_t)i * es] : mk<V>((T)0, (T)0);
+          if constexpr (single) v[q] = (i < n_x) ? line[i * es] : mk<V>((T)0, (T)0);
           else v[q] = lds[i * B + b];
         });
       }
@@ -236,7 +258,7 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
         if constexpr (L > 1) {
           static_for<R - 1>([&](auto q_) AIM_AI {
             constexpr int q = decltype(q_)::value + 1;
-            v[q] = tw_mul<false>(v[q], tw, j * q);
+            v[q] = tw_mul<false>(v[q], twl, j * q);
           });
         }
         Dft<R, false, V>::run(v);
@@ -251,7 +273,7 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
           constexpr int p = decltype(p_)::value;
           const int i = p * L + j;
           if constexpr (single) {
-            if (i < n_x) line[(int64_t)i * es] = v[p];
+            if (i < n_x) line[i * es] = v[p];
           } else {
             lds[i * B + b] = v[p];
           }
@@ -269,7 +291,7 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
         auto ld = [&](int i) AIM_AI -> V { return lds[i * B + b]; };
         auto st = [&](int i, V v) AIM_AI {
           if constexpr (last) {
-            if (i < n_x) line[(int64_t)i * es] = v;
+            if (i < n_x) line_b[(i - beta) * es] = v;
           } else {
             lds[i * B + b] = v;
           }
@@ -277,7 +299,7 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
         V v[R];
         if (active) stage_load<R, true, V>(v, beta, Mp, ld);
         if constexpr (!last) __syncthreads();
-        if (active) stage_compute_store<R, true, V>(v, beta, L, Mp, tw, st);
+        if (active) stage_compute_store<R, true, V>(v, beta, L, Mp, twl, st);
         if constexpr (!last) __syncthreads();
       });
     }
@@ -289,7 +311,7 @@ void launch_contig(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t lin
                    int64_t out_ls, bool inverse, const cx<T> *tw, hipStream_t s) {
   constexpr int B = tile_contig<T, PC>();
   constexpr int threads = threads_contig<T, PC>();
-  const size_t lds = PC::ns > 1 ? (size_t)B * (PC::P + 1) * sizeof(cx<T>) : 0;
+  const size_t lds = PC::ns > 1 ? ((size_t)B * (PC::P + 1) + PC::P) * sizeof(cx<T>) : 0;
   const int64_t blocks = (lines + B - 1) / B;
   if (inverse)
     hipLaunchKernelGGL((k_fft_contig<T, true, PC>), dim3((unsigned)blocks), dim3(threads), lds, s,
@@ -307,7 +329,7 @@ void launch_strided(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t ou
   constexpr int B = tile_strided<T, PC>();
   constexpr int threads = threads_strided<T, PC>();
   const int ntile = (int)((inner + B - 1) / B);
-  const size_t lds = PC::ns > 1 ? (size_t)PC::P * B * sizeof(cx<T>) : 0;
+  const size_t lds = PC::ns > 1 ? (size_t)PC::P * (B + 1) * sizeof(cx<T>) : 0;
   const int64_t blocks = outer * ntile;
   if (inverse)
     hipLaunchKernelGGL((k_fft_strided<T, true, PC>), dim3((unsigned)blocks), dim3(threads), lds, s,
@@ -324,7 +346,7 @@ void launch_mid(cx<T> *data, int n_x, int nfield, int Py, int Pz, int Hy, int Hz
   constexpr int B = tile_strided<T, PC>();
   constexpr int threads = threads_strided<T, PC>();
   const int ntile = (Pz + B - 1) / B;
-  const size_t lds = PC::ns > 1 ? (size_t)PC::P * B * sizeof(cx<T>) : 0;
+  const size_t lds = (size_t)PC::P * ((PC::ns > 1 ? B : 0) + 1) * sizeof(cx<T>);
   const int64_t tiles = ((int64_t)Py * ntile + kXcd - 1) / kXcd * kXcd;
   const int64_t blocks = tiles * nfield;
   hipLaunchKernelGGL((k_fft_mid<T, PC>), dim3((unsigned)blocks), dim3(threads), lds, s, data, n_x,

@@ -163,7 +163,9 @@ void host_plan_build(const aim_mesh &m, const aim_params &p, HostPlan *hp) {
   }
   int64_t V0 = (int64_t)h.grid[0] * h.grid[1] * h.grid[2];
   int64_t Vp = (int64_t)h.grid[0] * h.pad[1] * h.pad[2];
-  if (V0 > INT32_MAX / 2 || Vp > INT32_MAX / 2) fail_arg("grid too large for 32-bit indexing");
+  const int64_t Vf = (int64_t)h.pad[0] * h.pad[1] * h.pad[2];  // Green's spectrum set-up grid
+  if (V0 > INT32_MAX / 2 || Vp > INT32_MAX / 2 || Vf > INT32_MAX / 2)
+    fail_arg("grid too large for 32-bit indexing");
 
   // anchors: round-half-up((c - x0)/h) - M/2 (even M), floor(.) - (M-1)/2 (odd M), clamped
   h.anchor.resize(3 * n);

@@ -16,54 +16,72 @@ namespace aim {
 
 namespace {
 
-// Gather form: grid node v sums Lambda_T[e] x_{col[e]} over its entries, so
-// every node (also empty ones) is written exactly once and no atomics or
-// clearing pass are needed. One thread per node, in grid order.
+// Gather form of anterpolation: grid node v sums Lambda_T[e] x_{col[e]} over
+// its entries, so every node (also empty ones) is written exactly once, with
+// no atomics and no clearing pass, in a fixed order (bitwise reproducible).
+// Each 64-lane wave owns 64 consecutive nodes, whose entries are contiguous:
+// the wave loads them 64 at a time (coalesced), each lane forming one entry's
+// four products in LDS, and every lane then sums the slots of its own node.
 template <typename T, typename TX>
 __global__ void __launch_bounds__(256)
     k_anterp_gather(const cx<TX> *__restrict__ x, int64_t ldx, int nrhs,
                     const int32_t *__restrict__ node_ptr, const int32_t *__restrict__ ent_col,
                     const T *__restrict__ lamT, cx<T> *__restrict__ grid, int64_t V0) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= V0) return;
-  const int e0 = node_ptr[v], e1 = node_ptr[v + 1];
+  __shared__ cx<T> slot[4][64][4];  // [wave][entry][q]
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t v0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + w) * 64;
+  if (v0 >= V0) return;  // whole wave exits; no block-wide barrier is used
+  const int64_t v = v0 + lane;
+  const bool ok = v < V0;
+  const int64_t vend = (v0 + 64 < V0) ? v0 + 64 : V0;
+  const int e0 = ok ? node_ptr[v] : 0, e1 = ok ? node_ptr[v + 1] : 0;
+  const int w0 = node_ptr[v0], w1 = node_ptr[vend];
   for (int r = 0; r < nrhs; ++r) {
     const cx<TX> *xr = x + (int64_t)r * ldx;
     T a[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-    // entries in groups of 4 so that their independent loads overlap
-    for (int e = e0; e < e1; e += 4) {
-      int c[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) c[k] = (e + k < e1) ? ent_col[e + k] : -1;
-      cx<TX> xv[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        xv[k].x = 0;
-        xv[k].y = 0;
-        if (c[k] >= 0) xv[k] = xr[c[k]];
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (c[k] < 0) break;
-        const T xa = (T)xv[k].x, xb = (T)xv[k].y;
+    for (int c0 = w0; c0 < w1; c0 += 64) {
+      const int e = c0 + lane;
+      if (e < w1) {
+        const cx<TX> xv = xr[ent_col[e]];
+        const T xa = (T)xv.x, xb = (T)xv.y;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const T w = lamT[(int64_t)(e + k) * 4 + q];
-          a[q][0] += w * xa;
-          a[q][1] += w * xb;
+          const T wq = lamT[(int64_t)e * 4 + q];
+          cx<T> p;
+          p.x = wq * xa;
+          p.y = wq * xb;
+          slot[w][lane][q] = p;
         }
       }
-    }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int lo = (e0 > c0 ? e0 : c0) - c0, hi = (e1 < c0 + 64 ? e1 : c0 + 64) - c0;
+      for (int k = lo; k < hi; ++k) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      cx<T> o;
-      o.x = a[q][0];
-      o.y = a[q][1];
-      grid[((int64_t)(r * 4 + q)) * V0 + v] = o;
+        for (int q = 0; q < 4; ++q) {
+          const cx<T> p = slot[w][k][q];
+          a[q][0] += p.x;
+          a[q][1] += p.y;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (ok) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cx<T> o;
+        o.x = a[q][0];
+        o.y = a[q][1];
+        grid[((int64_t)(r * 4 + q)) * V0 + v] = o;
+      }
     }
   }
 }
 
+// kz-blocked [F][Pz/blk][Nx][Py][blk] grid -> plain [F][Nx][Py][Pz] (inspection)
 template <typename T>
 __global__ void k_unblock(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, int64_t F, int Nx,
                           int Py, int Pz, int blk, int64_t fstride) {
@@ -78,17 +96,17 @@ __global__ void k_unblock(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
 }
 
 template <typename V>
-__device__ __forceinline__ V wave_sum(V v) {
+__device__ __forceinline__ V half_wave_sum(V v) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    v.x += __shfl_xor(v.x, off, 64);
-    v.y += __shfl_xor(v.y, off, 64);
+  for (int off = 16; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, 32);
+    v.y += __shfl_xor(v.y, off, 32);
   }
   return v;
 }
 
 // y_m = j k eta [sum_{q<3} Lambda_mq . phi_q - k^-2 Lambda_md . phi_d]
-//       + sum_n Z^near_mn x_n. One 64-lane wave per row m.
+//       + sum_n Z^near_mn x_n. One 32-lane half-wave per row m.
 template <typename T, typename TX, typename TY>
 __global__ void __launch_bounds__(256)
     k_interp_near(const cx<T> *__restrict__ phi, int64_t V0, int nrhs, const T *__restrict__ lam,
@@ -97,9 +115,9 @@ __global__ void __launch_bounds__(256)
                   const cx<T> *__restrict__ nearv, const cx<TX> *__restrict__ x, int64_t ldx,
                   cx<TY> *__restrict__ y, int64_t ldy, int64_t n, T keta, T inv_k2) {
   using V = cx<T>;
-  const int lane = threadIdx.x & 63;
-  const int64_t m = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (m >= n) return;
+  const int lane = threadIdx.x & 31;
+  const int64_t m = (int64_t)blockIdx.x * (blockDim.x >> 5) + (threadIdx.x >> 5);
+  if (m >= n) return;  // both rows of a wave exit together or each half runs alone
   const int64_t a = anchor_lin[m];
   const int e0 = rowptr[m], e1 = rowptr[m + 1];
   for (int r = 0; r < nrhs; ++r) {
@@ -107,7 +125,7 @@ __global__ void __launch_bounds__(256)
     far.x = 0;
     far.y = 0;
     const V *ph = phi + (int64_t)(r * 4) * V0 + a;
-    for (int u = lane; u < K; u += 64) {
+    for (int u = lane; u < K; u += 32) {
       const int64_t o = soff[u];
       const T l0 = lam[(m * 4 + 0) * K + u], l1 = lam[(m * 4 + 1) * K + u];
       const T l2 = lam[(m * 4 + 2) * K + u], l3 = lam[(m * 4 + 3) * K + u];
@@ -119,7 +137,7 @@ __global__ void __launch_bounds__(256)
     nr.x = 0;
     nr.y = 0;
     const cx<TX> *xr = x + (int64_t)r * ldx;
-    for (int e = e0 + lane; e < e1; e += 64) {
+    for (int e = e0 + lane; e < e1; e += 32) {
       const V z = nearv[e];
       const cx<TX> xv = xr[cols[e]];
       const T xa = (T)xv.x, xb = (T)xv.y;
@@ -129,7 +147,7 @@ __global__ void __launch_bounds__(256)
     V acc;
     acc.x = -keta * far.y + nr.x;  // j k eta * far
     acc.y = keta * far.x + nr.y;
-    acc = wave_sum(acc);
+    acc = half_wave_sum(acc);
     if (lane == 0) {
       cx<TY> out;
       out.x = (decltype(out.x))acc.x;
@@ -255,9 +273,9 @@ void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, 
   far_stages<T, TX>(pl, md, nrhs, x, ldx, 6, s, ev);
   const cx<T> *phi = (const cx<T> *)pl->work[prec][0];
   const int64_t V0 = (int64_t)h.grid[0] * h.grid[1] * h.grid[2];
-  const int rows_per_block = 4;
+  const int rows_per_block = 8;
   const int64_t blocks = (h.n + rows_per_block - 1) / rows_per_block;
-  hipLaunchKernelGGL((k_interp_near<T, TX, TY>), dim3((unsigned)blocks), dim3(64 * rows_per_block),
+  hipLaunchKernelGGL((k_interp_near<T, TX, TY>), dim3((unsigned)blocks), dim3(32 * rows_per_block),
                      0, s, phi, V0, nrhs, lam_of<T>(md), md.anchor_lin, md.stencil_off, h.K,
                      md.rowptr, md.cols, near_of<T>(md), x, ldx, y, ldy, h.n,
                      (T)(h.k * kEta0), (T)(1.0 / (h.k * h.k)));
