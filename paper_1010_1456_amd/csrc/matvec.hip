@@ -234,13 +234,14 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
   (void)Px;
   const int64_t F = 4 * (int64_t)nrhs;
   const int64_t V0 = (int64_t)Nx * Ny * Nz;
-  const int64_t V1 = (int64_t)Nx * Ny * Pz;
   const int blk = kGridBlock<T>;
+  const int Pzs = (Pz + blk - 1) / blk * blk;  // z rows padded to 128-byte multiples
+  const int64_t V1 = (int64_t)Nx * Ny * Pzs;
   const int64_t V2 = (int64_t)Nx * Py * ((Pz + blk - 1) / blk * blk);  // kz-blocked
   cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * V0);
   cx<T> *g1 = (cx<T> *)work_buffer(pl, prec, 1, sizeof(cx<T>) * F * V1);
   cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2);
-  const fftk::LineMap m1 = fftk::plain_map((int64_t)Ny * Pz, Pz);
+  const fftk::LineMap m1 = fftk::plain_map((int64_t)Ny * Pzs, Pzs);
   const fftk::LineMap m2 = fftk::blocked_map(V2, Nx, Py, blk);
   mark(0);
   hipLaunchKernelGGL((k_anterp_gather<T, TX>), dim3((unsigned)((V0 + 255) / 256)), dim3(256), 0, s,
@@ -248,7 +249,7 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
   LAUNCHCHECK();
   mark(1);
   if (stop <= 1) return;
-  fft_pass_contig(g0, g1, md.plan[2], Nz, Pz, F * Nx * Ny, Nz, Pz, false, tw_of<T>(md, 2), s);
+  fft_pass_contig(g0, g1, md.plan[2], Nz, Pz, F * Nx * Ny, Nz, Pzs, false, tw_of<T>(md, 2), s);
   mark(2);
   if (stop <= 2) return;
   fft_pass_strided(g1, g2, md.plan[1], Ny, Py, F * Nx, Pz, m1, m2, false, tw_of<T>(md, 1), s);
@@ -261,7 +262,7 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
   fft_pass_strided(g2, g1, md.plan[1], Py, Ny, F * Nx, Pz, m2, m1, true, tw_of<T>(md, 1), s);
   mark(5);
   if (stop <= 5) return;
-  fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * Nx * Ny, Pz, Nz, true, tw_of<T>(md, 2), s);
+  fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * Nx * Ny, Pzs, Nz, true, tw_of<T>(md, 2), s);
   mark(6);
 }
 
@@ -299,9 +300,13 @@ void copy_far_stage(Plan *pl, MeshDev &md, int nrhs, int stage, void *out, hipSt
     LAUNCHCHECK();
     return;
   }
-  const int64_t sz = (stage == 2 || stage == 5) ? (int64_t)Nx * Ny * Pz : (int64_t)Nx * Ny * Nz;
-  const int which = (stage == 2 || stage == 5) ? 1 : 0;
-  HIPCHECK(hipMemcpyAsync(out, pl->work[prec][which], sizeof(cx<T>) * F * sz,
+  if (stage == 2 || stage == 5) {  // drop the row padding
+    const int Pzs = (Pz + blk - 1) / blk * blk;
+    HIPCHECK(hipMemcpy2DAsync(out, sizeof(cx<T>) * Pz, pl->work[prec][1], sizeof(cx<T>) * Pzs,
+                              sizeof(cx<T>) * Pz, (size_t)(F * Nx * Ny), hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  HIPCHECK(hipMemcpyAsync(out, pl->work[prec][0], sizeof(cx<T>) * F * Nx * Ny * Nz,
                           hipMemcpyDeviceToDevice, s));
 }
 template void copy_far_stage<double>(Plan *, MeshDev &, int, int, void *, hipStream_t);
