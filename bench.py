@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "AIM matvec/s + % HBM roofline, mixed vs FP64 at equal RCS err (sphere 8λ)"
 STAGES = ["projection", "fwd_z", "fwd_y", "x_green", "inv_y", "inv_z", "interp_near"]
-KERNELS = ["k_anterp", "k_fft_contig", "k_fft_strided", "k_fft_mid", "k_fft_strided",
+KERNELS = ["k_anterp_fftz", "k_fft_contig", "k_fft_strided", "k_fft_mid", "k_fft_strided",
            "k_fft_contig", "k_interp_near"]
 
 
@@ -39,7 +39,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def stage_bytes(info, mesh, nrhs, s_grid, s_real, s_x, s_y):
+def stage_bytes(info, mesh, nrhs, s_grid, s_real, s_x, s_y, path):
     """Algorithmic HBM bytes of each step of one product: every operator datum
     read once, vectors read/written once, grid fields per the pruned passes."""
     n = info["n"][mesh]
@@ -51,9 +51,13 @@ def stage_bytes(info, mesh, nrhs, s_grid, s_real, s_x, s_y):
     F = 4 * nrhs
     H = (Px // 2 + 1) * (Py // 2 + 1) * (Pz // 2 + 1)
     lam = n * (4 * K * s_real + 4)
+    if info["fused_projection"][mesh][path]:  # projection inside the forward z pass
+        proj, fwdz = lam + nrhs * n * s_x + F * V1 * s_grid, 0.0
+    else:
+        proj, fwdz = F * V0 * s_grid + lam + nrhs * n * s_x, F * (V0 + V1) * s_grid
     return np.array([
-        F * V0 * s_grid + lam + nrhs * n * s_x,                       # projection
-        F * (V0 + V1) * s_grid,                                        # forward z
+        proj,                                                          # projection (+ forward z)
+        fwdz,                                                          # forward z
         F * (V1 + V2) * s_grid,                                        # forward y
         2 * F * V2 * s_grid + H * s_grid,                              # x pass + spectrum
         F * (V2 + V1) * s_grid,                                        # inverse y
@@ -164,10 +168,10 @@ def main(argv=None):
     y = torch.empty_like(x)
 
     res = {}
-    for name, prec, sg, sr in (("mixed", A.AIM_MIXED_IO64, 8, 4), ("fp64", A.AIM_FP64, 16, 8)):
+    for name, prec, sg, sr, path in (("mixed", A.AIM_MIXED_IO64, 8, 4, 1), ("fp64", A.AIM_FP64, 16, 8, 0)):
         log(f"[bench] timing {name}: {args.warmup} warm-up + {args.steps} products")
         wall, st_ms, tot_ms = time_path(plan, A, prec, x, y, args.steps, args.warmup)
-        b = stage_bytes(info, 0, R, sg, sr, 16, 16)
+        b = stage_bytes(info, 0, R, sg, sr, 16, 16, path)
         res[name] = dict(wall=wall, stage_ms=st_ms, total_ms=tot_ms, bytes=b)
         log(f"[bench] {name}: {wall / args.steps * 1e3:.3f} ms/product, stages(ms)="
             + ",".join(f"{v:.3f}" for v in st_ms))
@@ -202,10 +206,12 @@ def main(argv=None):
                                f"N={n}, grid {info['grid'][0]}, FFT {info['pad'][0]}, "
                                f"near nnz {info['nnz_total']}; nrhs={R}"),
             "precision": "c64 grid/stencil/near arithmetic on c128 vectors (mixed path)",
+            "fused_projection": info["fused_projection"][0][1],
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": f"{KERNELS[d]} ({STAGES[d]})",
+            "kernel": (("k_anterp_fftz" if info["fused_projection"][0][1] else "k_anterp_gather")
+                       if d == 0 else KERNELS[d]) + f" ({STAGES[d]})",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -220,7 +226,8 @@ def main(argv=None):
             "frac": total_bytes / (mx["wall"] / args.steps) / 1e9 / HBM_PEAK_GBS,
         },
         "stage_ms": {s: float(v) for s, v in zip(STAGES, mx["stage_ms"])},
-        "stage_GBs": {s: float(b / (v * 1e-3) / 1e9) for s, b, v in zip(STAGES, mx["bytes"], mx["stage_ms"])},
+        "stage_GBs": {s: float(b / (v * 1e-3) / 1e9) for s, b, v in zip(STAGES, mx["bytes"], mx["stage_ms"])
+                      if b > 0},
         "fp64": {
             "value": R * args.steps / res["fp64"]["wall"],
             "ms_per_step": res["fp64"]["wall"] / args.steps * 1e3,

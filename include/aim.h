@@ -116,7 +116,8 @@ typedef struct {
 
 /* Sizes of a plan (per mesh and totals). bytes_* are the algorithmic HBM
  * bytes of one single-RHS product in each precision: operator data read once,
- * vectors read/written once, grid traffic of the pruned pass structure. */
+ * vectors read/written once, grid traffic of the pruned pass structure used
+ * (with fused_projection, the projected grid is never stored). */
 typedef struct {
   int32_t nmesh;
   int32_t order;
@@ -132,6 +133,9 @@ typedef struct {
   double k[AIM_MAX_MESH];               /* wavenumber, 1/m */
   double bytes_fp64[AIM_MAX_MESH];
   double bytes_mixed[AIM_MAX_MESH];
+  int32_t fused_projection[AIM_MAX_MESH][2]; /* [mesh][0 FP64, 1 mixed]: 1 if the projection
+                                               runs inside the forward z pass (chosen by
+                                               timing at set-up) */
   double device_bytes;                  /* device memory held by the plan */
 } aim_info;
 
@@ -165,7 +169,9 @@ typedef struct aim_host_plan aim_host_plan;
  * (mesh validation, RWG table, grid, stencil anchors, near-zone pattern),
  * then on the GPU the projection weights, the spectrum of the grid Green's
  * function, and the FP64 near-zone matrix Z^MOM - Z^grid with singularity
- * extraction on touching triangle pairs. Unknowns of mesh i occupy rows
+ * extraction on touching triangle pairs; finally it times the alternative
+ * kernel variants of each mesh and keeps the faster (results do not depend
+ * on the choice beyond rounding). Unknowns of mesh i occupy rows
  * offset[i] .. offset[i]+n[i]-1. Synchronises hip_stream. On failure *out is
  * NULL and nothing leaks. */
 aim_status aim_setup(const aim_mesh *meshes, int32_t nmesh, const aim_params *p,

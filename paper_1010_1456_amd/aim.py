@@ -77,7 +77,7 @@ class AimInfo(ctypes.Structure):
                 ("nnz", c_int64 * M), ("grid", (c_int32 * 3) * M), ("pad", (c_int32 * 3) * M),
                 ("h", c_double * M), ("x0", (c_double * 3) * M), ("k", c_double * M),
                 ("bytes_fp64", c_double * M), ("bytes_mixed", c_double * M),
-                ("device_bytes", c_double)]
+                ("fused_projection", (c_int32 * 2) * M), ("device_bytes", c_double)]
 
 
 class AimSolveOpts(ctypes.Structure):
@@ -267,7 +267,10 @@ class Plan:
             pad=[tuple(inf.pad[i]) for i in range(nm)], h=[inf.h[i] for i in range(nm)],
             x0=[tuple(inf.x0[i]) for i in range(nm)], k=[inf.k[i] for i in range(nm)],
             bytes_fp64=[inf.bytes_fp64[i] for i in range(nm)],
-            bytes_mixed=[inf.bytes_mixed[i] for i in range(nm)], device_bytes=inf.device_bytes)
+            bytes_mixed=[inf.bytes_mixed[i] for i in range(nm)],
+            fused_projection=[(bool(inf.fused_projection[i][0]), bool(inf.fused_projection[i][1]))
+                              for i in range(nm)],
+            device_bytes=inf.device_bytes)
 
     def _stream(self, stream):
         s = stream if stream is not None else self._torch.cuda.current_stream()

@@ -38,6 +38,13 @@ struct FftPlan {
 };
 bool fft_plan_for(int P, FftPlan *out);  // false if P has no supported factorisation
 int fft_length_at_least(int lo);        // smallest supported length >= lo
+// true if the projection has a kernel fused with the forward pass of length
+// pl.P (all butterflies of 4 lines fit one work-group)
+inline bool fft_anterp_fused(const FftPlan &pl) {
+  int m = 0;
+  for (int s = 0; s < pl.ns; ++s) m = pl.P / pl.r[s] > m ? pl.P / pl.r[s] : m;
+  return 4 * m <= 1024;
+}
 
 // ---------------------------------------------------------------------------
 // Host plan of one mesh (no GPU involved).
@@ -118,6 +125,9 @@ struct MeshDev {
   int32_t *ent_col = nullptr;   // n_entries
   double *lamT64 = nullptr;     // n_entries * 4
   float *lamT32 = nullptr;      // n_entries * 4
+  // tuned variants, per precision [0 = FP64, 1 = FP32]: projection fused with
+  // the forward z pass (1) or two launches (0)
+  int fuse_proj[2] = {0, 0};
 };
 
 struct Plan;
@@ -147,6 +157,8 @@ struct Plan {
 
 // set-up kernels (setup_kernels.hip)
 void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s);
+// times the alternative kernel variants of one mesh and keeps the faster
+void autotune_mesh(Plan *pl, MeshDev &md, hipStream_t s);
 
 namespace fftk {
 struct LineMap;
@@ -166,6 +178,18 @@ struct LineMap;
 AIM_DECLARE_FFT(float2)
 AIM_DECLARE_FFT(double2)
 #undef AIM_DECLARE_FFT
+
+// anterpolation fused with the forward z pass (fft_anterp_*.hip): x (c64 or
+// c128) -> forward z transforms of the 4 source fields, [4 nrhs][nlines][out_ls]
+#define AIM_DECLARE_ANTERP(VX, T, V)                                                             \
+  bool anterp_fftz(const VX *x, int64_t ldx, int nrhs, const int32_t *node_ptr,                  \
+                   const int32_t *ent_col, const T *lamT, int Nz, int64_t nlines, V *out,        \
+                   int64_t out_ls, int64_t out_fstride, const V *tw, const FftPlan &pl,          \
+                   hipStream_t s);
+AIM_DECLARE_ANTERP(float2, float, float2)
+AIM_DECLARE_ANTERP(double2, float, float2)
+AIM_DECLARE_ANTERP(double2, double, double2)
+#undef AIM_DECLARE_ANTERP
 
 // matvec (matvec.hip)
 // `ev` (optional) receives an event record before the first kernel and after

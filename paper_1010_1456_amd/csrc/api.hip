@@ -88,9 +88,10 @@ static double model_bytes(const MeshDev &md, int sc, int sr) {
   const double nearb = nnz * (sc + 4.0) + 4.0 * (n + 1.0);
   const double ghat = (double)md.H[0] * md.H[1] * md.H[2] * sc;
   const double V0 = Nx * Ny * Nz, V1 = Nx * Ny * Pz, V2 = Nx * Py * Pz;
-  // per field: anterp write V0; z: V0 + V1; y: V1 + V2; mid: 2 V2; inv y: V2 + V1;
-  // inv z: V1 + V0; interp read V0
-  const double grid = 4.0 * sc * (4.0 * V0 + 4.0 * V1 + 4.0 * V2);
+  // per field: [projection write V0; z read V0] + z write V1; y: V1 + V2; x: 2 V2;
+  // inverse y: V2 + V1; inverse z: V1 + V0; interpolation read V0
+  const double v0_terms = md.fuse_proj[sc == 16 ? 0 : 1] ? 2.0 : 4.0;
+  const double grid = 4.0 * sc * (v0_terms * V0 + 4.0 * V1 + 4.0 * V2);
   return vec + lam + nearb + ghat + grid;
 }
 
@@ -173,6 +174,7 @@ aim_status aim_setup(const aim_mesh *meshes, int32_t nmesh, const aim_params *p,
     pl->n_total = off;
     if (off > INT32_MAX) throw Error(AIM_ERR_ARG, "too many unknowns");
     for (int i = 0; i < nmesh; ++i) setup_mesh_device(pl.get(), pl->mesh[i], pl->setup_stream);
+    for (int i = 0; i < nmesh; ++i) autotune_mesh(pl.get(), pl->mesh[i], pl->setup_stream);
     HIPCHECK(hipStreamSynchronize(pl->setup_stream));
   });
   if (st != AIM_OK) {
@@ -204,6 +206,8 @@ aim_status aim_plan_info(const aim_plan *plan, aim_info *out) {
     out->k[i] = md.hp.k;
     out->bytes_fp64[i] = model_bytes(md, 16, 8);
     out->bytes_mixed[i] = model_bytes(md, 8, 4);
+    out->fused_projection[i][0] = md.fuse_proj[0];
+    out->fused_projection[i][1] = md.fuse_proj[1];
   }
   out->device_bytes = plan->device_bytes;
   return AIM_OK;

@@ -244,12 +244,20 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
   const fftk::LineMap m1 = fftk::plain_map((int64_t)Ny * Pzs, Pzs);
   const fftk::LineMap m2 = fftk::blocked_map(V2, Nx, Py, blk);
   mark(0);
-  hipLaunchKernelGGL((k_anterp_gather<T, TX>), dim3((unsigned)((V0 + 255) / 256)), dim3(256), 0, s,
-                     x, ldx, nrhs, md.node_ptr, md.ent_col, lamT_of<T>(md), g0, V0);
-  LAUNCHCHECK();
-  mark(1);
-  if (stop <= 1) return;
-  fft_pass_contig(g0, g1, md.plan[2], Nz, Pz, F * Nx * Ny, Nz, Pzs, false, tw_of<T>(md, 2), s);
+  // projection fused with the forward z pass: the projected grid is never
+  // stored (except for inspection, or for FFT lengths without a fused kernel)
+  if (stop <= 1 || !md.fuse_proj[prec] ||
+      !anterp_fftz(x, ldx, nrhs, md.node_ptr, md.ent_col, lamT_of<T>(md), Nz, (int64_t)Nx * Ny, g1,
+                   Pzs, (int64_t)Nx * Ny * Pzs, tw_of<T>(md, 2), md.plan[2], s)) {
+    hipLaunchKernelGGL((k_anterp_gather<T, TX>), dim3((unsigned)((V0 + 255) / 256)), dim3(256), 0,
+                       s, x, ldx, nrhs, md.node_ptr, md.ent_col, lamT_of<T>(md), g0, V0);
+    LAUNCHCHECK();
+    mark(1);
+    if (stop <= 1) return;
+    fft_pass_contig(g0, g1, md.plan[2], Nz, Pz, F * Nx * Ny, Nz, Pzs, false, tw_of<T>(md, 2), s);
+  } else {
+    mark(1);
+  }
   mark(2);
   if (stop <= 2) return;
   fft_pass_strided(g1, g2, md.plan[1], Ny, Py, F * Nx, Pz, m1, m2, false, tw_of<T>(md, 1), s);
@@ -311,6 +319,54 @@ void copy_far_stage(Plan *pl, MeshDev &md, int nrhs, int stage, void *out, hipSt
 }
 template void copy_far_stage<double>(Plan *, MeshDev &, int, int, void *, hipStream_t);
 template void copy_far_stage<float>(Plan *, MeshDev &, int, int, void *, hipStream_t);
+
+void autotune_mesh(Plan *pl, MeshDev &md, hipStream_t s) {
+  const int64_t n = md.hp.n;
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0));
+  HIPCHECK(hipEventCreate(&e1));
+  void *x = nullptr;
+  try {
+    x = dev_alloc(pl, sizeof(double2) * n);
+    HIPCHECK(hipMemsetAsync(x, 0, sizeof(double2) * n, s));
+    for (int prec = 0; prec < 2; ++prec) {
+      if (prec == 1 && !pl->mixed) break;
+      if (!fft_anterp_fused(md.plan[2])) {
+        md.fuse_proj[prec] = 0;
+        continue;
+      }
+      float best = 0;
+      int choice = 0;
+      for (int v = 0; v < 2; ++v) {
+        md.fuse_proj[prec] = v;
+        for (int rep = 0; rep < 4; ++rep) {  // first repetition is a warm-up
+          if (rep == 1) HIPCHECK(hipEventRecord(e0, s));
+          if (prec == 0)
+            far_stages<double, double>(pl, md, 1, (const double2 *)x, n, 2, s);
+          else
+            far_stages<float, double>(pl, md, 1, (const double2 *)x, n, 2, s);
+        }
+        HIPCHECK(hipEventRecord(e1, s));
+        HIPCHECK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+        if (v == 0 || ms < best) {
+          best = ms;
+          choice = v;
+        }
+      }
+      md.fuse_proj[prec] = choice;
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (x) dev_free(pl, x);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  dev_free(pl, x);
+}
 
 template void far_stages<double, double>(Plan *, MeshDev &, int, const double2 *, int64_t, int,
                                          hipStream_t, hipEvent_t *);
