@@ -70,6 +70,16 @@ template <typename T, class PC>
 constexpr int threads_strided() {
   return round_up_c(PC::maxnb() * tile_strided<T, PC>(), 64);
 }
+// x pass: lines per work-group (128-byte rows; 64- and 256-byte rows measured
+// slower on the 324-point plan)
+template <typename T, class PC>
+constexpr int tile_mid() {
+  return tile_strided<T, PC>();
+}
+template <typename T, class PC>
+constexpr int threads_mid() {
+  return round_up_c(PC::maxnb() * tile_mid<T, PC>(), 64);
+}
 template <typename T, class PC>
 constexpr int tile_contig() {
   int B = 256 / PC::maxnb();
@@ -186,7 +196,7 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
 constexpr int kXcd = 8;
 
 template <typename T, class PC>
-__global__ void __launch_bounds__((threads_strided<T, PC>()))
+__global__ void __launch_bounds__((threads_mid<T, PC>()))
     k_fft_mid(cx<T> *__restrict__ data, int n_x, int nfield, int Py, int Pz, int ntile, int Hy,
               int Hz, const cx<T> *__restrict__ ghat, const cx<T> *__restrict__ tw, int, int blk,
               int64_t fstride) {
@@ -194,7 +204,7 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
   extern __shared__ unsigned char smem_raw[];
   V *lds = reinterpret_cast<V *>(smem_raw);
   constexpr int P = PC::P, ns = PC::ns;
-  constexpr int B = tile_strided<T, PC>();
+  constexpr int B = tile_mid<T, PC>();
   const int xcd = blockIdx.x % kXcd;
   const int jb = blockIdx.x / kXcd;
   const int field = jb % nfield;
@@ -343,8 +353,8 @@ void launch_strided(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t ou
 template <typename T, class PC>
 void launch_mid(cx<T> *data, int n_x, int nfield, int Py, int Pz, int Hy, int Hz,
                 const cx<T> *ghat, const cx<T> *tw, int blk, int64_t fstride, hipStream_t s) {
-  constexpr int B = tile_strided<T, PC>();
-  constexpr int threads = threads_strided<T, PC>();
+  constexpr int B = tile_mid<T, PC>();
+  constexpr int threads = threads_mid<T, PC>();
   const int ntile = (Pz + B - 1) / B;
   const size_t lds = (size_t)PC::P * ((PC::ns > 1 ? B : 0) + 1) * sizeof(cx<T>);
   const int64_t tiles = ((int64_t)Py * ntile + kXcd - 1) / kXcd * kXcd;
