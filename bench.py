@@ -120,6 +120,44 @@ def cpu_baseline(mesh, cfg, nrhs, pad):
     }
 
 
+def solve_compare(plan, A, mesh, workload, iters):
+    """The x-polarised wave toward -z solved by both paths (GMRES(100), Jacobi,
+    tol 1e-4, fixed iteration budget): time per iteration, residuals, and the
+    RCS agreement err_tt(mixed, fp64) on a 2-degree grid; for spheres also
+    err_tt against the Mie series."""
+    import torch
+
+    from oracle import farfield as off
+    from oracle import mie as omie
+    from oracle.constants import wavenumber
+
+    th, ph = off.rcs_grid(2.0)
+    res = {}
+    for name, prec in (("mixed", A.AIM_MIXED), ("fp64", A.AIM_FP64)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st = plan.solve([(0.0, 0.0, 0)], prec, tol=1e-4, restart=100, max_iter=iters,
+                           raise_on_noconv=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sig = plan.rcs(x, th, ph)[0, 0]
+        res[name] = dict(seconds=dt, iterations=st[0]["iterations"], residual=st[0]["residual"],
+                         converged=st[0]["converged"], matvec_low=st[0]["matvec_low"],
+                         matvec_fp64=st[0]["matvec_fp64"], ms_per_iteration=dt / max(1, st[0]["iterations"]) * 1e3,
+                         sigma=sig)
+        log(f"[bench] solve {name}: {st[0]['iterations']} its, residual {st[0]['residual']:.3e}, {dt:.2f} s")
+    out = {k: {kk: vv for kk, vv in v.items() if kk != "sigma"} for k, v in res.items()}
+    out["err_tt_mixed_vs_fp64"] = off.err_tt(res["mixed"]["sigma"], res["fp64"]["sigma"], th)
+    if workload.startswith("sphere"):
+        k = wavenumber(mesh.freq_hz)
+        sm = omie.sigma_tt(k, float(workload[len("sphere"):]) * mesh.lam, th, ph)
+        for name in ("mixed", "fp64"):
+            out[name]["err_tt_vs_mie"] = off.err_tt(res[name]["sigma"], sm, th)
+    out["mixed_speedup_per_iteration"] = res["fp64"]["ms_per_iteration"] / res["mixed"]["ms_per_iteration"]
+    out["setting"] = f"GMRES(100), right Jacobi, tol 1e-4, at most {iters} iterations, x-pol wave toward -z"
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +166,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="sphere8", choices=["sphere8", "plate16", "plate1", "plate128"])
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--solve-iters", type=int, default=300,
+                    help="GMRES iteration budget of the solve comparison (0 skips it)")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run a plain elementwise copy of 256 MiB (3 launches) whose "
                          "FETCH_SIZE/WRITE_SIZE counters calibrate the HBM byte counts")
@@ -240,6 +280,8 @@ def main(argv=None):
         "setup_s": setup_s,
         "device_bytes": info["device_bytes"],
     }
+    if args.solve_iters > 0:
+        out["solve"] = solve_compare(plan, A, mesh, args.workload, args.solve_iters)
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(mesh, cfg, R, tuple(info["pad"][0]))

@@ -4,8 +4,8 @@
 // RMS residual (Section 2.2). Here every (mesh, plane wave) pair is its own
 // system; all systems advance in lock-step so one batched AIM product serves
 // them all. Arnoldi runs in FP64 on the device (classical Gram-Schmidt, two
-// passes); only the new Hessenberg column crosses to the host per iteration,
-// where the Givens rotations and the convergence test run. For AIM_MIXED the
+// passes), and so do the Givens rotations and the residual estimate; the host
+// only polls the per-system active flags every few iterations. For AIM_MIXED the
 // inner solves use the c64 operator on c128 Krylov vectors, inside an FP64
 // iterative-refinement loop r = b - A64 x that decides convergence.
 #include <chrono>
@@ -17,8 +17,6 @@
 namespace aim {
 
 namespace {
-
-using zc = std::complex<double>;
 
 constexpr int kRed = 256;
 
@@ -48,22 +46,42 @@ __device__ inline double2 block_sum2(double a, double b) {
   return make_double2(ra, rb);
 }
 
-// h[i*S + s] += sum_rows conj(V[i][r][row]) w[r][row], s = sys0 + r
-__global__ void __launch_bounds__(kRed)
-    k_dots(const double2 *V, const double2 *w, int64_t ld, int64_t vstride, int64_t lo, int64_t hi,
-           int sys0, int S, double2 *h) {
-  const int i = blockIdx.y, r = blockIdx.z;
-  const double2 *v = V + (int64_t)i * vstride + (int64_t)r * ld;
-  const double2 *ww = w + (int64_t)r * ld;
-  double a = 0, b = 0;
-  for (int64_t n = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < hi;
-       n += (int64_t)gridDim.x * blockDim.x) {
-    const double2 p = v[n], q = ww[n];
-    a += p.x * q.x + p.y * q.y;
-    b += p.x * q.y - p.y * q.x;
+// All nv dot products of one Gram-Schmidt pass in one launch: every thread
+// keeps its kRows entries of w in registers and walks a group of kGroup basis
+// vectors (blockIdx.z); h[i*S + s] += sum_rows conj(V[i][r][row]) w[r][row]
+// via one atomic per wave.
+constexpr int kRows = 4;
+constexpr int kGroup = 8;
+__global__ void __launch_bounds__(256)
+    k_dots_all(const double2 *V, const double2 *w, int64_t ld, int64_t vstride, int64_t lo,
+               int64_t hi, int nv, int sys0, int S, double2 *h) {
+  const int r = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  double2 wv[kRows];
+  int64_t idx[kRows];
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) {
+    idx[k] = lo + ((int64_t)blockIdx.x * kRows + k) * blockDim.x + threadIdx.x;
+    wv[k] = idx[k] < hi ? w[(int64_t)r * ld + idx[k]] : make_double2(0.0, 0.0);
   }
-  const double2 t = block_sum2(a, b);
-  if (threadIdx.x == 0) atomic_add2(&h[(int64_t)i * S + sys0 + r], t.x, t.y);
+  const int i1 = min(nv, (int)(blockIdx.z + 1) * kGroup);
+  for (int i = blockIdx.z * kGroup; i < i1; ++i) {
+    const double2 *v = V + (int64_t)i * vstride + (int64_t)r * ld;
+    double a = 0, b = 0;
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      if (idx[k] < hi) {
+        const double2 p = v[idx[k]];
+        a += p.x * wv[k].x + p.y * wv[k].y;
+        b += p.x * wv[k].y - p.y * wv[k].x;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      a += __shfl_xor(a, off, 64);
+      b += __shfl_xor(b, off, 64);
+    }
+    if (lane == 0) atomic_add2(&h[(int64_t)i * S + sys0 + r], a, b);
+  }
 }
 
 // w[r][row] -= sum_{i<nv} h[i*S + s] V[i][r][row]
@@ -201,17 +219,110 @@ void norms(Ctx &c, const double2 *v, double *dscratch, std::vector<double> &out)
   HIPCHECK(hipStreamSynchronize(c.s));
 }
 
+// ---- device-side Givens rotations and back substitution (one thread per
+// system). Complex values as double2.
+__device__ inline double2 cmul_(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cconjmul_(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+struct GmresDev {
+  double2 *H;      // [S][(m+1) m], column j of system s at H[s][i*m + j]
+  double2 *cs, *sn;  // [S][m]
+  double2 *g;      // [S][m+1]
+  int *active;     // [S]
+  int *its;        // [S] iterations counted
+  int *jend;       // [S] columns of the current cycle
+  double *tol_abs;  // [S] stop when |g_{j+1}| <= tol_abs
+};
+
+// New Hessenberg column j of every active system: sum of the two Gram-Schmidt
+// passes and the norm; apply the previous rotations, form the new one, update
+// the residual estimate |g_{j+1}|.
+__global__ void k_givens(GmresDev d, const double2 *h1, const double2 *h2, const double *nrm, int j,
+                         int m, int S) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S || !d.active[s]) return;
+  double2 *Hs = d.H + (int64_t)s * (m + 1) * m;
+  double2 *cs = d.cs + (int64_t)s * m, *sn = d.sn + (int64_t)s * m;
+  double2 *g = d.g + (int64_t)s * (m + 1);
+  for (int i = 0; i <= j; ++i) {
+    const double2 a = h1[(int64_t)i * S + s], b = h2[(int64_t)i * S + s];
+    Hs[i * m + j] = make_double2(a.x + b.x, a.y + b.y);
+  }
+  double2 hj1 = make_double2(sqrt(nrm[s]), 0.0);
+  for (int i = 0; i < j; ++i) {
+    const double2 hi = Hs[i * m + j];
+    const double2 hn = Hs[(i + 1) * m + j];
+    // [hi; hn] <- [conj(c) hi + conj(s) hn; -s hi + c hn]
+    const double2 t0 = cconjmul_(cs[i], hi), t1 = cconjmul_(sn[i], hn);
+    const double2 u0 = cmul_(sn[i], hi), u1 = cmul_(cs[i], hn);
+    Hs[i * m + j] = make_double2(t0.x + t1.x, t0.y + t1.y);
+    Hs[(i + 1) * m + j] = make_double2(u1.x - u0.x, u1.y - u0.y);
+  }
+  const double2 a = Hs[j * m + j];
+  const double den = sqrt(a.x * a.x + a.y * a.y + hj1.x * hj1.x);
+  double2 c, sv;
+  if (den == 0.0) {
+    c = make_double2(1.0, 0.0);
+    sv = make_double2(0.0, 0.0);
+  } else {
+    c = make_double2(a.x / den, a.y / den);
+    sv = make_double2(hj1.x / den, 0.0);
+  }
+  cs[j] = c;
+  sn[j] = sv;
+  Hs[j * m + j] = make_double2(den, 0.0);
+  Hs[(j + 1) * m + j] = make_double2(0.0, 0.0);
+  const double2 gj = g[j];
+  const double2 gn = cmul_(sv, gj);
+  g[j + 1] = make_double2(-gn.x, -gn.y);
+  g[j] = cconjmul_(c, gj);
+  d.its[s] += 1;
+  d.jend[s] = j + 1;
+  const double res = sqrt(gn.x * gn.x + gn.y * gn.y);
+  if (res <= d.tol_abs[s] || den == 0.0) d.active[s] = 0;
+}
+
+// y = H^-1 g on the jend x jend upper triangle (y stored [i][s] like h)
+__global__ void k_backsub(GmresDev d, double2 *y, int m, int S) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const int n = d.jend[s];
+  const double2 *Hs = d.H + (int64_t)s * (m + 1) * m;
+  const double2 *g = d.g + (int64_t)s * (m + 1);
+  for (int i = n - 1; i >= 0; --i) {
+    double2 acc = g[i];
+    for (int k = i + 1; k < n; ++k) {
+      const double2 t = cmul_(Hs[i * m + k], y[(int64_t)k * S + s]);
+      acc.x -= t.x;
+      acc.y -= t.y;
+    }
+    const double2 hd = Hs[i * m + i];
+    const double dd = hd.x * hd.x + hd.y * hd.y;
+    y[(int64_t)i * S + s] = dd == 0.0 ? make_double2(0.0, 0.0)
+                                      : make_double2((acc.x * hd.x + acc.y * hd.y) / dd,
+                                                     (acc.y * hd.x - acc.x * hd.y) / dd);
+  }
+}
+
 struct Work {
   double2 *V = nullptr;  // (m+1) x R x ld
   double2 *z = nullptr, *w = nullptr;
   double2 *h1 = nullptr, *h2 = nullptr, *y = nullptr;
   double *nrm = nullptr;
-  int *nv = nullptr;
+  GmresDev dev{};
 };
 
+constexpr int kCheckEvery = 8;  // iterations between convergence checks on the host
+
 // Solve A d = rhs (d starts at 0) for every system to a relative residual
-// tol_s (estimated by the Arnoldi recurrence), restarted every m steps.
-// Returns the inner iterations used; `its` per system, `low` counts products.
+// tol_s (estimated by the Arnoldi recurrence), restarted every m steps. The
+// Arnoldi step, the rotations and the residual estimate stay on the device;
+// the host reads the active flags every kCheckEvery iterations. Returns the
+// iterations used (lock-step count); `its` per system, `nprod` products.
 int gmres_run(Ctx &c, aim_precision prec, Work &wk, int m, const double2 *rhs, double2 *d,
               const std::vector<double> &rhs_norm2, const std::vector<double> &tol_s, int max_iter,
               std::vector<int> &its, int &nprod) {
@@ -224,6 +335,8 @@ int gmres_run(Ctx &c, aim_precision prec, Work &wk, int m, const double2 *rhs, d
   int total = 0;
   std::vector<double> r2;
   bool first_cycle = true;
+  std::vector<int> act(S), itd(S);
+  HIPCHECK(hipMemcpyAsync(wk.dev.its, its.data(), sizeof(int) * S, hipMemcpyHostToDevice, c.s));
   while (true) {
     // residual of the current iterate: r = rhs - A d (rhs itself on the first cycle)
     if (first_cycle) {
@@ -241,8 +354,8 @@ int gmres_run(Ctx &c, aim_precision prec, Work &wk, int m, const double2 *rhs, d
       if (!done[s] && r2[s] <= tol_s[s] * tol_s[s] * rhs_norm2[s]) done[s] = 1;
       all &= (bool)done[s];
     }
-    if (all || total >= max_iter) return total;
-    // V[0] = r / |r|
+    if (all || total >= max_iter) break;
+    // V[0] = r / |r|; cycle state on the device
     {
       int mi = 0;
       for (auto &md : c.pl->mesh) {
@@ -252,17 +365,18 @@ int gmres_run(Ctx &c, aim_precision prec, Work &wk, int m, const double2 *rhs, d
         ++mi;
       }
     }
-    std::vector<std::vector<zc>> H(S, std::vector<zc>((m + 1) * m, 0.0));
-    std::vector<std::vector<zc>> cs(S, std::vector<zc>(m)), sn(S, std::vector<zc>(m));
-    std::vector<std::vector<zc>> g(S, std::vector<zc>(m + 1, 0.0));
-    std::vector<int> jend(S, 0);
-    std::vector<char> active(S);
+    std::vector<double2> g0((size_t)S * (m + 1), make_double2(0, 0));
+    std::vector<double> tabs(S);
     for (int s = 0; s < S; ++s) {
-      g[s][0] = std::sqrt(r2[s]);
-      active[s] = !done[s];
+      act[s] = !done[s];
+      g0[(size_t)s * (m + 1)] = make_double2(std::sqrt(r2[s]), 0.0);
+      tabs[s] = tol_s[s] * std::sqrt(rhs_norm2[s]);
     }
-    std::vector<double2> hh1((size_t)(m + 1) * S), hh2((size_t)(m + 1) * S);
-    std::vector<double> nn(S);
+    std::vector<int> zero(S, 0);
+    HIPCHECK(hipMemcpyAsync(wk.dev.g, g0.data(), sizeof(double2) * g0.size(), hipMemcpyHostToDevice, c.s));
+    HIPCHECK(hipMemcpyAsync(wk.dev.active, act.data(), sizeof(int) * S, hipMemcpyHostToDevice, c.s));
+    HIPCHECK(hipMemcpyAsync(wk.dev.tol_abs, tabs.data(), sizeof(double) * S, hipMemcpyHostToDevice, c.s));
+    HIPCHECK(hipMemcpyAsync(wk.dev.jend, zero.data(), sizeof(int) * S, hipMemcpyHostToDevice, c.s));
     for (int j = 0; j < m && total < max_iter; ++j) {
       // w = A D^-1 V[j]
       hipLaunchKernelGGL(k_precond, dim3(nblk(ld, 256)), dim3(256), 0, c.s, wk.V + j * vstride, wk.z,
@@ -277,8 +391,10 @@ int gmres_run(Ctx &c, aim_precision prec, Work &wk, int m, const double2 *rhs, d
         HIPCHECK(hipMemsetAsync(h, 0, sizeof(double2) * (j + 1) * S, c.s));
         int mi = 0;
         for (auto &md : c.pl->mesh) {
-          hipLaunchKernelGGL(k_dots, dim3(red_blocks(md.hp.n), j + 1, R), dim3(kRed), 0, c.s, wk.V,
-                             wk.w, ld, vstride, md.offset, md.offset + md.hp.n, mi * R, S, h);
+          hipLaunchKernelGGL(k_dots_all, dim3(nblk(md.hp.n, 256 * kRows), R, nblk(j + 1, kGroup)),
+                             dim3(256), 0, c.s,
+                             wk.V, wk.w, ld, vstride, md.offset, md.offset + md.hp.n, j + 1, mi * R, S,
+                             h);
           LAUNCHCHECK();
           hipLaunchKernelGGL(k_sub_basis, dim3(nblk(md.hp.n, 256), R), dim3(256), 0, c.s, wk.V,
                              wk.w, ld, vstride, md.offset, md.offset + md.hp.n, j + 1, mi * R, S, h);
@@ -300,66 +416,25 @@ int gmres_run(Ctx &c, aim_precision prec, Work &wk, int m, const double2 *rhs, d
           ++mi;
         }
       }
-      HIPCHECK(hipMemcpyAsync(hh1.data(), wk.h1, sizeof(double2) * (j + 1) * S, hipMemcpyDeviceToHost, c.s));
-      HIPCHECK(hipMemcpyAsync(hh2.data(), wk.h2, sizeof(double2) * (j + 1) * S, hipMemcpyDeviceToHost, c.s));
-      HIPCHECK(hipMemcpyAsync(nn.data(), wk.nrm, sizeof(double) * S, hipMemcpyDeviceToHost, c.s));
-      HIPCHECK(hipStreamSynchronize(c.s));
-      bool any_active = false;
-      for (int s = 0; s < S; ++s) {
-        if (!active[s]) continue;
-        its[s]++;
-        zc *Hc = &H[s][0];
-        for (int i = 0; i <= j; ++i)
-          Hc[i * m + j] = zc(hh1[(size_t)i * S + s].x + hh2[(size_t)i * S + s].x,
-                             hh1[(size_t)i * S + s].y + hh2[(size_t)i * S + s].y);
-        Hc[(j + 1) * m + j] = std::sqrt(nn[s]);
-        for (int i = 0; i < j; ++i) {
-          zc t = std::conj(cs[s][i]) * Hc[i * m + j] + std::conj(sn[s][i]) * Hc[(i + 1) * m + j];
-          Hc[(i + 1) * m + j] = -sn[s][i] * Hc[i * m + j] + cs[s][i] * Hc[(i + 1) * m + j];
-          Hc[i * m + j] = t;
-        }
-        zc a = Hc[j * m + j], b = Hc[(j + 1) * m + j];
-        double den = std::sqrt(std::norm(a) + std::norm(b));
-        if (den == 0) {
-          cs[s][j] = 1;
-          sn[s][j] = 0;
-        } else {
-          cs[s][j] = a / den;
-          sn[s][j] = b / den;
-        }
-        Hc[j * m + j] = den;
-        Hc[(j + 1) * m + j] = 0;
-        g[s][j + 1] = -sn[s][j] * g[s][j];
-        g[s][j] = std::conj(cs[s][j]) * g[s][j];
-        jend[s] = j + 1;
-        if (std::abs(g[s][j + 1]) <= tol_s[s] * std::sqrt(rhs_norm2[s]) || den == 0) active[s] = 0;
-        any_active |= (bool)active[s];
+      hipLaunchKernelGGL(k_givens, dim3(nblk(S, 64)), dim3(64), 0, c.s, wk.dev, wk.h1, wk.h2, wk.nrm,
+                         j, m, S);
+      LAUNCHCHECK();
+      if ((j + 1) % kCheckEvery == 0 || j == m - 1) {
+        HIPCHECK(hipMemcpyAsync(act.data(), wk.dev.active, sizeof(int) * S, hipMemcpyDeviceToHost, c.s));
+        HIPCHECK(hipStreamSynchronize(c.s));
+        bool any = false;
+        for (int s = 0; s < S; ++s) any |= (bool)act[s];
+        if (!any) break;
       }
-      if (!any_active) break;
     }
-    // d += D^-1 V y, y = H^-1 g per system
-    std::vector<double2> yv((size_t)m * S, make_double2(0, 0));
-    std::vector<int> nv(S);
-    int nv_max = 0;
-    for (int s = 0; s < S; ++s) {
-      const int n = done[s] ? 0 : jend[s];
-      nv[s] = n;
-      nv_max = std::max(nv_max, n);
-      std::vector<zc> y(n);
-      for (int i = n - 1; i >= 0; --i) {
-        zc acc = g[s][i];
-        for (int k = i + 1; k < n; ++k) acc -= H[s][i * m + k] * y[k];
-        y[i] = H[s][i * m + i] == zc(0) ? zc(0) : acc / H[s][i * m + i];
-      }
-      for (int i = 0; i < n; ++i) yv[(size_t)i * S + s] = make_double2(y[i].real(), y[i].imag());
-    }
-    HIPCHECK(hipMemcpyAsync(wk.y, yv.data(), sizeof(double2) * m * S, hipMemcpyHostToDevice, c.s));
-    HIPCHECK(hipMemcpyAsync(wk.nv, nv.data(), sizeof(int) * S, hipMemcpyHostToDevice, c.s));
+    // d += D^-1 V y, y = H^-1 g per system (systems done before the cycle: jend = 0)
+    hipLaunchKernelGGL(k_backsub, dim3(nblk(S, 64)), dim3(64), 0, c.s, wk.dev, wk.y, m, S);
+    LAUNCHCHECK();
     {
       int mi = 0;
       for (auto &md : c.pl->mesh) {
         hipLaunchKernelGGL(k_update_x, dim3(nblk(md.hp.n, 256), R), dim3(256), 0, c.s, wk.V, d,
-                           c.dinv, ld, vstride, md.offset, md.offset + md.hp.n, nv_max, wk.nv,
+                           c.dinv, ld, vstride, md.offset, md.offset + md.hp.n, m, wk.dev.jend,
                            mi * R, S, wk.y);
         LAUNCHCHECK();
         ++mi;
@@ -367,6 +442,10 @@ int gmres_run(Ctx &c, aim_precision prec, Work &wk, int m, const double2 *rhs, d
     }
     HIPCHECK(hipStreamSynchronize(c.s));
   }
+  HIPCHECK(hipMemcpyAsync(itd.data(), wk.dev.its, sizeof(int) * S, hipMemcpyDeviceToHost, c.s));
+  HIPCHECK(hipStreamSynchronize(c.s));
+  for (int s = 0; s < S; ++s) its[s] = itd[s];
+  return total;
 }
 
 }  // namespace
@@ -394,7 +473,14 @@ aim_status gmres_solve(Plan *pl, aim_precision prec, int R, const aim_planewave 
     wk.h2 = (double2 *)alloc(sizeof(double2) * (size_t)(m + 1) * S);
     wk.y = (double2 *)alloc(sizeof(double2) * (size_t)(m + 1) * S);
     wk.nrm = (double *)alloc(sizeof(double) * S);
-    wk.nv = (int *)alloc(sizeof(int) * S);
+    wk.dev.H = (double2 *)alloc(sizeof(double2) * (size_t)S * (m + 1) * m);
+    wk.dev.cs = (double2 *)alloc(sizeof(double2) * (size_t)S * m);
+    wk.dev.sn = (double2 *)alloc(sizeof(double2) * (size_t)S * m);
+    wk.dev.g = (double2 *)alloc(sizeof(double2) * (size_t)S * (m + 1));
+    wk.dev.active = (int *)alloc(sizeof(int) * S);
+    wk.dev.its = (int *)alloc(sizeof(int) * S);
+    wk.dev.jend = (int *)alloc(sizeof(int) * S);
+    wk.dev.tol_abs = (double *)alloc(sizeof(double) * S);
     double2 *b = (double2 *)alloc(sizeof(double2) * cnt);
     double2 *r = (double2 *)alloc(sizeof(double2) * cnt);
     double2 *dd = (double2 *)alloc(sizeof(double2) * cnt);
