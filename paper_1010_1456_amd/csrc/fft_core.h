@@ -150,10 +150,12 @@ struct Dft<3, INV, V> {
     V t1 = add(v[1], v[2]);
     V d = sub(v[1], v[2]);
     V t2 = mk<V>(v[0].x - (T)0.5 * t1.x, v[0].y - (T)0.5 * t1.y);
-    V rot = mul_mi<INV>(mk<V>(s3 * d.x, s3 * d.y));  // -+ i s3 (v1 - v2)
+    // X1, X2 = t2 -+ i s3 d (forward) / t2 +- i s3 d (inverse); written as
+    // multiply-adds so the scaled difference is never formed on its own
+    const T sg = INV ? -s3 : s3;
     v[0] = add(v[0], t1);
-    v[1] = add(t2, rot);
-    v[2] = sub(t2, rot);
+    v[1] = mk<V>(t2.x + sg * d.y, t2.y - sg * d.x);
+    v[2] = mk<V>(t2.x - sg * d.y, t2.y + sg * d.x);
   }
 };
 
@@ -226,6 +228,33 @@ struct Dft<R, INV, V, std::enable_if_t<(R > 3 && smallest_factor(R) != R)>> {
   }
 };
 
+// Length-R DFT (R even) of a vector whose upper half v[R/2..R-1] is zero and
+// is not read: the first radix-2 layer of the composite split degenerates to
+// copies, leaving the two half-length DFTs of v and of v twisted by
+// exp(-+ 2 pi i q / R). Outputs in natural order as Dft<R>::run.
+template <int R, bool INV, typename V>
+__host__ __device__ __forceinline__ void dft_upper_zero(V *v) {
+  static_assert(R % 2 == 0, "upper-half-zero DFT needs an even length");
+  if constexpr (R == 2) {
+    v[1] = v[0];
+  } else {
+    constexpr int B = R / 2;
+    V e[B], o[B];
+    static_for<B>([&](auto q_) AIM_AI {
+      constexpr int q = decltype(q_)::value;
+      e[q] = v[q];
+      o[q] = twc<R, q, INV>(v[q]);
+    });
+    Dft<B, INV, V>::run(e);
+    Dft<B, INV, V>::run(o);
+    static_for<B>([&](auto p_) AIM_AI {
+      constexpr int p = decltype(p_)::value;
+      v[2 * p] = e[p];
+      v[2 * p + 1] = o[p];
+    });
+  }
+}
+
 // Twiddle exp(-+ 2 pi i e / P) from a table of exp(-2 pi i e / P).
 template <bool INV, typename V>
 __host__ __device__ __forceinline__ V tw_mul(V a, const V *tw, int e) {
@@ -241,23 +270,51 @@ __device__ __forceinline__ void stage_load(V *v, int beta, int Mp, Ld &ld) {
   int base = j * R * Mp + kp;
   static_for<R>([&](auto q_) AIM_AI { v[decltype(q_)::value] = ld(base + decltype(q_)::value * Mp); });
 }
+// first NIN inputs only (the others are known to be zero)
+template <int R, int NIN, typename V, class Ld>
+__device__ __forceinline__ void stage_load_p(V *v, int beta, int Mp, Ld &ld) {
+  int j = beta / Mp, kp = beta - j * Mp;
+  int base = j * R * Mp + kp;
+  static_for<NIN>([&](auto q_) AIM_AI { v[decltype(q_)::value] = ld(base + decltype(q_)::value * Mp); });
+}
 
-template <int R, bool INV, typename V, class St>
-__device__ __forceinline__ void stage_compute_store(V *v, int beta, int L, int Mp, const V *tw,
-                                                    St &st) {
+// UZ: the upper half of the butterfly's inputs is zero (first stage of a
+// transform whose line holds at most P/2 inputs, R even). NOUT: only outputs
+// p < NOUT are stored (last stage of a transform of which at most the first
+// P/2 outputs are kept: NOUT = R/2); the rest is never computed. ROWS: tw is
+// a per-stage table of rows tw[j (R - 1) + q - 1] = exp(-2 pi i j M' q / P)
+// (one row per butterfly group j, so a thread reads its twiddles at fixed
+// offsets from one address) instead of the table of exp(-2 pi i e / P).
+template <int R, bool INV, bool UZ, int NOUT, bool ROWS, typename V, class St>
+__device__ __forceinline__ void stage_compute_store_p(V *v, int beta, int L, int Mp, const V *tw,
+                                                      St &st) {
   int j = beta / Mp, kp = beta - j * Mp;
   if (L > 1) {
-    int step = j * Mp;
-    static_for<R - 1>([&](auto q_) AIM_AI {
-      constexpr int q = decltype(q_)::value + 1;
-      v[q] = tw_mul<INV>(v[q], tw, step * q);
-    });
+    if constexpr (ROWS) {
+      const V *row = tw + j * (R - 1);
+      static_for<R - 1>([&](auto q_) AIM_AI {
+        constexpr int q = decltype(q_)::value + 1;
+        v[q] = tw_mul<INV>(v[q], row, q - 1);
+      });
+    } else {
+      int step = j * Mp;
+      static_for<R - 1>([&](auto q_) AIM_AI {
+        constexpr int q = decltype(q_)::value + 1;
+        v[q] = tw_mul<INV>(v[q], tw, step * q);
+      });
+    }
   }
-  Dft<R, INV, V>::run(v);
-  static_for<R>([&](auto p_) AIM_AI {
+  if constexpr (UZ) dft_upper_zero<R, INV, V>(v);
+  else Dft<R, INV, V>::run(v);
+  static_for<NOUT>([&](auto p_) AIM_AI {
     constexpr int p = decltype(p_)::value;
     st((j + L * p) * Mp + kp, v[p]);
   });
+}
+template <int R, bool INV, typename V, class St>
+__device__ __forceinline__ void stage_compute_store(V *v, int beta, int L, int Mp, const V *tw,
+                                                    St &st) {
+  stage_compute_store_p<R, INV, false, R, false>(v, beta, L, Mp, tw, st);
 }
 
 // Supported radices; the dispatch macro expands a body once per radix with

@@ -188,131 +188,256 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
   });
 }
 
-// x pass over data in the kz-blocked layout [nfield][Pz/blk][n_x][Py][blk]
-// (blk == 0: plain [nfield][n_x][Py][Pz]): lines (ky, kz), tile over kz. One
-// work-group per (tile, field). Work-groups are dealt round-robin to the 8
-// XCDs, so block ids are arranged for the fields of one tile to land on the
-// same XCD back to back and share its L2 copy of the spectrum tile.
+// x pass over data in the kz-blocked layout [nfield][Pz/blk][n_x][Py][blk]:
+// lines (ky, kz). A work-group owns a tile of B consecutive kz (B | blk, so
+// the tile lies in one kz block) at one ky in one field and runs the forward
+// transform, spectrum multiply and inverse transform of its lines. The
+// fields of a tile, and the fields of its mirror tile Py - ky (the same
+// octant rows), get consecutive numbers, and consecutive numbers go to the
+// same XCD (work-groups are dealt round-robin to the 8 XCDs), so the octant
+// rows a tile reads are mostly found in that XCD's L2. Global accesses are buffer
+// loads and stores: a work-group-uniform resource and scalar offset plus a
+// per-thread 32-bit offset fixed for the whole kernel (the launcher checks
+// the ranges), which keeps address arithmetic off the vector ALU.
 constexpr int kXcd = 8;
+constexpr int kBufferWord3 = 0x00020000;  // raw buffer resource, 32-bit data format
+
+using u32x2 = unsigned int __attribute__((ext_vector_type(2)));
+using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                           kBufferWord3);
+}
+template <typename V>
+__device__ __forceinline__ V bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(V) == 8)
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+  else
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+template <typename V>
+__device__ __forceinline__ void bstore(V v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                       uint32_t soff) {
+  if constexpr (sizeof(V) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, (int)voff, (int)soff,
+                                           0);
+}
+
+// waves per SIMD the x pass must fit in registers (its LDS allows about 4)
+template <typename T>
+constexpr int mid_min_waves() {
+  return sizeof(T) == 4 ? 4 : 3;
+}
+// LDS of the x pass: the tile's lines, the twiddle table (3-stage plans), and
+// the row tables of the middle stage and of the inverse's last stage
+template <typename T, class PC>
+struct MidLds {
+  static constexpr int P = PC::P, ns = PC::ns, R0 = PC::r(0), RM = PC::r(ns - 1);
+  static constexpr int data = ns > 1 ? P * tile_mid<T, PC>() : 0;
+  static constexpr int flat = ns > 2 ? P : 0;
+  static constexpr int mid_rows = ns > 1 ? (P / RM) * (RM - 1) : 0;
+  static constexpr bool same_rows = (R0 == RM);  // square two-stage plans share one table
+  static constexpr int last_rows = (ns > 1 && !same_rows) ? (P / R0) * (R0 - 1) : 0;
+  static constexpr int total = data + flat + mid_rows + last_rows;
+};
 
 template <typename T, class PC>
-__global__ void __launch_bounds__((threads_mid<T, PC>()))
-    k_fft_mid(cx<T> *__restrict__ data, int n_x, int nfield, int Py, int Pz, int ntile, int Hy,
-              int Hz, const cx<T> *__restrict__ ghat, const cx<T> *__restrict__ tw, int, int blk,
+__global__ void __launch_bounds__((threads_mid<T, PC>()), (mid_min_waves<T>()))
+    k_fft_mid(cx<T> *__restrict__ data, int n_x, int nfield, int Py, int Pz, int ntile, int slots,
+              int Hy, int Hz, const cx<T> *__restrict__ ghat, const cx<T> *__restrict__ tw, int blk,
               int64_t fstride) {
   using V = cx<T>;
+  using ML = MidLds<T, PC>;
   extern __shared__ unsigned char smem_raw[];
   V *lds = reinterpret_cast<V *>(smem_raw);
   constexpr int P = PC::P, ns = PC::ns;
   constexpr int B = tile_mid<T, PC>();
-  const int xcd = blockIdx.x % kXcd;
-  const int jb = blockIdx.x / kXcd;
-  const int field = jb % nfield;
-  const int tile = (jb / nfield) * kXcd + xcd;
-  if (tile >= Py * ntile) return;  // padding blocks: exit before any barrier
-  const int ky = tile / ntile;
-  const int kz0 = (tile % ntile) * B;
+  constexpr uint32_t SV = sizeof(V);
+  // a line holds at most P/2 sources (n_x <= P/2 for even P, checked by the
+  // launcher) and only its first P/2 outputs are kept: with an even first
+  // radix the forward transform's first stage skips the zero upper half of
+  // its inputs and the inverse transform's last stage (same radix) computes
+  // the lower half of its outputs only
+  constexpr bool HALF = (PC::r(0) % 2 == 0);
+  constexpr int R0 = PC::r(0), Mp0 = P / R0;      // first stage: L = 1, M' = nb = P / R0
+  constexpr int NIN0 = HALF ? R0 / 2 : R0;        // first-stage inputs per butterfly
+  constexpr int RM = PC::r(ns - 1), LM = P / RM;  // middle stage (M' = 1)
+
+  // work number t = nfield (2 (fky ntile + kzt) + m) + field, ky = fky (m = 0)
+  // or Py - fky (m = 1)
+  const int t = (int)(blockIdx.x % kXcd) * slots + (int)(blockIdx.x / kXcd);
+  const int field = t % nfield, tt = t / nfield;
+  const int m = tt & 1, rest = tt >> 1;
+  const int fky = rest / ntile;
+  const int kzt = rest - fky * ntile;
+  if (2 * fky > Py) return;                      // padding: exit before any barrier
+  if (m && (fky == 0 || 2 * fky == Py)) return;  // row is its own mirror: m = 0 covers it
+  const int ky = m ? Py - fky : fky;
+  const int kz0 = kzt * B;
   const int b = threadIdx.x % B;
   const int beta = threadIdx.x / B;
   const int kz = kz0 + b;
   const bool line_ok = kz < Pz;
-  const int fky = (ky <= Py - ky) ? ky : Py - ky;
   const int fkz = (kz <= Pz - kz) ? kz : Pz - kz;
-  const int gofs = fky * Hz + fkz;  // octant offsets fit in 32 bits
   const int gplane = Hy * Hz;
-  const int es = blk == 0 ? Py * Pz : Py * blk;  // x stride (32-bit, checked by the planner)
-  V *twl = lds + (ns > 1 ? P * B : 0);
-  for (int i = threadIdx.x; i < P; i += blockDim.x) twl[i] = tw[i];
-  __syncthreads();
-  const int64_t lofs = blk == 0 ? (int64_t)ky * Pz + kz
-                                : (int64_t)(kz / blk) * n_x * es + (int64_t)ky * blk + kz % blk;
+  const int es = Py * blk;  // elements between x and x + 1 of a line
+  // field data: resource over the tile's kz block of this field; the tile's
+  // first line starts at byte t0 of it, thread (b, beta) adds o_beta
+  const int64_t blk_elems = (int64_t)n_x * es;
+  const __amdgpu_buffer_rsrc_t fr =
+      buffer_of(data + field * fstride + (int64_t)(kz0 / blk) * blk_elems,
+                (uint32_t)blk_elems * SV);
+  const uint32_t t0 = (uint32_t)(ky * blk + kz0 % blk) * SV;
+  const uint32_t o_beta = (uint32_t)(b + beta * es) * SV;
 
-  {
-    V *line = data + field * fstride + lofs;
-    V *line_b = line + beta * es;  // element beta of the line
-    // forward stages except the last
-    static_for<ns - 1>([&](auto s_) AIM_AI {
-      constexpr int s = decltype(s_)::value;
+  // spectrum values of the middle butterfly j = beta (kx = j + LM p): kx <
+  // P/2 for 2p <= RM - 2 (row kx), kx >= P/2 for 2p >= RM (row P - kx); only
+  // the middle p of an odd RM is folded at run time. Loaded where they are
+  // used: issued at entry they delay the first stage's loads.
+  const int j = beta;
+  const bool act_mid = line_ok && (beta < LM);
+  auto spectrum = [&](V *g) AIM_AI {
+    const int gofs = fky * Hz + fkz;
+    const __amdgpu_buffer_rsrc_t gres =
+        buffer_of(ghat, (uint32_t)gplane * (uint32_t)(P / 2 + 1) * SV);
+    const uint32_t g_lo = (uint32_t)(j * gplane + gofs) * SV;
+    const uint32_t g_hi = (uint32_t)((LM - 1 - j) * gplane + gofs) * SV;
+    static_for<RM>([&](auto p_) AIM_AI {
+      constexpr int p = decltype(p_)::value;
+      if constexpr (2 * p <= RM - 2) {
+        g[p] = bload<V>(gres, g_lo, (uint32_t)(LM * p * gplane) * SV);
+      } else if constexpr (2 * p >= RM) {
+        g[p] = bload<V>(gres, g_hi, (uint32_t)((P - LM * p - LM + 1) * gplane) * SV);
+      } else {
+        const int kx = j + LM * p;
+        const int fkx = (kx <= P - kx) ? kx : P - kx;
+        g[p] = bload<V>(gres, (uint32_t)(fkx * gplane + gofs) * SV, 0u);
+      }
+    });
+  };
+
+  // first-stage inputs: butterfly beta reads elements beta + q M' (q < NIN0)
+  const bool act0 = line_ok && (beta < Mp0);
+  V v0[R0];
+  if (act0)
+    static_for<NIN0>([&](auto q_) AIM_AI {
+      constexpr int q = decltype(q_)::value;
+      v0[q] = (beta + q * Mp0 < n_x) ? bload<V>(fr, o_beta, t0 + (uint32_t)(q * Mp0 * es) * SV)
+                                     : mk<V>((T)0, (T)0);
+    });
+
+  V *twl = lds + ML::data;                            // flat table (3-stage plans)
+  V *twm = twl + ML::flat;                            // middle stage rows
+  V *twr = ML::same_rows ? twm : twm + ML::mid_rows;  // inverse last stage rows
+  if constexpr (ML::flat > 0)
+    for (int i = threadIdx.x; i < P; i += blockDim.x) twl[i] = tw[i];
+  if constexpr (ns > 1) {
+    for (int i = threadIdx.x; i < ML::mid_rows; i += blockDim.x) {
+      const int jj = i / (RM - 1), q = i - jj * (RM - 1) + 1;
+      twm[i] = tw[jj * q];
+    }
+    if constexpr (!ML::same_rows)
+      for (int i = threadIdx.x; i < ML::last_rows; i += blockDim.x) {
+        const int jj = i / (R0 - 1), q = i - jj * (R0 - 1) + 1;
+        twr[i] = tw[jj * q];
+      }
+  }
+
+  if constexpr (ns == 1) {
+    // one stage (L = 1, only beta = 0 works): forward DFT, multiply, inverse
+    // DFT, all in registers
+    if (act0) {
+      if constexpr (HALF) dft_upper_zero<R0, false, V>(v0);
+      else Dft<R0, false, V>::run(v0);
+      V g[R0];
+      spectrum(g);
+      static_for<R0>([&](auto p_) AIM_AI {
+        constexpr int p = decltype(p_)::value;
+        v0[p] = cmul(v0[p], g[p]);
+      });
+      Dft<R0, true, V>::run(v0);
+      static_for<NIN0>([&](auto p_) AIM_AI {
+        constexpr int p = decltype(p_)::value;
+        if (p < n_x) bstore(v0[p], fr, o_beta, t0 + (uint32_t)(p * es) * SV);
+      });
+    }
+  } else {
+    __syncthreads();  // twiddle tables ready
+    // first forward stage
+    {
+      auto st = [&](int i, V x) AIM_AI { lds[i * B + b] = x; };
+      if (act0) stage_compute_store_p<R0, false, HALF, R0, false>(v0, beta, 1, Mp0, twl, st);
+      __syncthreads();
+    }
+    // further forward stages but the last (3-stage plans)
+    static_for<ns - 2>([&](auto s_) AIM_AI {
+      constexpr int s = decltype(s_)::value + 1;
       constexpr int R = PC::r(s), L = PC::lb(s), Mp = P / (L * R), nb = P / R;
-      constexpr bool first = (s == 0);
       const bool active = line_ok && (beta < nb);
-      auto ld = [&](int i) AIM_AI -> V {
-        if constexpr (first) return (i < n_x) ? line_b[(i - beta) * es] : mk<V>((T)0, (T)0);
-        else return lds[i * B + b];
-      };
-      auto st = [&](int i, V v) AIM_AI { lds[i * B + b] = v; };
+      auto ld = [&](int i) AIM_AI -> V { return lds[i * B + b]; };
+      auto st = [&](int i, V x) AIM_AI { lds[i * B + b] = x; };
       V v[R];
       if (active) stage_load<R, false, V>(v, beta, Mp, ld);
-      if constexpr (!first) __syncthreads();
+      __syncthreads();
       if (active) stage_compute_store<R, false, V>(v, beta, L, Mp, twl, st);
       __syncthreads();
     });
     // last forward stage, spectrum multiply, first inverse stage in registers
     {
-      constexpr int R = PC::r(ns - 1);
-      constexpr int L = P / R;
-      constexpr bool single = (ns == 1);
-      const bool active = line_ok && (beta < L);
-      const int j = beta;
-      V v[R];
-      if (active) {
-        static_for<R>([&](auto q_) AIM_AI {
+      V v[RM];
+      if (act_mid)
+        static_for<RM>([&](auto q_) AIM_AI {
           constexpr int q = decltype(q_)::value;
-          const int i = j * R + q;
-          if constexpr (single) v[q] = (i < n_x) ? line[i * es] : mk<V>((T)0, (T)0);
-          else v[q] = lds[i * B + b];
+          v[q] = lds[(j * RM + q) * B + b];
         });
-      }
-      if constexpr (!single) __syncthreads();
-      if (active) {
-        if constexpr (L > 1) {
-          static_for<R - 1>([&](auto q_) AIM_AI {
-            constexpr int q = decltype(q_)::value + 1;
-            v[q] = tw_mul<false>(v[q], twl, j * q);
-          });
-        }
-        Dft<R, false, V>::run(v);
-        static_for<R>([&](auto p_) AIM_AI {
-          constexpr int p = decltype(p_)::value;
-          const int kx = j + L * p;
-          const int fkx = (kx <= P - kx) ? kx : P - kx;
-          v[p] = cmul(v[p], ghat[fkx * gplane + gofs]);
-        });
-        Dft<R, true, V>::run(v);
-        static_for<R>([&](auto p_) AIM_AI {
-          constexpr int p = decltype(p_)::value;
-          const int i = p * L + j;
-          if constexpr (single) {
-            if (i < n_x) line[i * es] = v[p];
-          } else {
-            lds[i * B + b] = v[p];
-          }
-        });
-      }
-    }
-    if constexpr (ns > 1) {
       __syncthreads();
-      // remaining inverse stages, radices in reverse order
-      static_for<ns - 1>([&](auto s_) AIM_AI {
-        constexpr int s = decltype(s_)::value + 1;
-        constexpr int R = PC::ri(s), L = PC::lbi(s), Mp = P / (L * R), nb = P / R;
-        constexpr bool last = (s == ns - 1);
-        const bool active = line_ok && (beta < nb);
-        auto ld = [&](int i) AIM_AI -> V { return lds[i * B + b]; };
-        auto st = [&](int i, V v) AIM_AI {
-          if constexpr (last) {
-            if (i < n_x) line_b[(i - beta) * es] = v;
-          } else {
-            lds[i * B + b] = v;
-          }
-        };
-        V v[R];
-        if (active) stage_load<R, true, V>(v, beta, Mp, ld);
-        if constexpr (!last) __syncthreads();
-        if (active) stage_compute_store<R, true, V>(v, beta, L, Mp, twl, st);
-        if constexpr (!last) __syncthreads();
-      });
+      if (act_mid) {
+        const V *row = twm + j * (RM - 1);
+        static_for<RM - 1>([&](auto q_) AIM_AI {
+          constexpr int q = decltype(q_)::value + 1;
+          v[q] = tw_mul<false>(v[q], row, q - 1);
+        });
+        Dft<RM, false, V>::run(v);
+        V g[RM];
+        spectrum(g);
+        static_for<RM>([&](auto p_) AIM_AI {
+          constexpr int p = decltype(p_)::value;
+          v[p] = cmul(v[p], g[p]);
+        });
+        Dft<RM, true, V>::run(v);
+        static_for<RM>([&](auto p_) AIM_AI {
+          constexpr int p = decltype(p_)::value;
+          lds[(p * LM + j) * B + b] = v[p];
+        });
+      }
+      __syncthreads();
     }
+    // remaining inverse stages, radices in reverse order; the last (M' = 1)
+    // writes elements beta + L p of its line
+    static_for<ns - 1>([&](auto s_) AIM_AI {
+      constexpr int s = decltype(s_)::value + 1;
+      constexpr int R = PC::ri(s), L = PC::lbi(s), Mp = P / (L * R), nb = P / R;
+      constexpr bool last = (s == ns - 1);
+      const bool active = line_ok && (beta < nb);
+      auto ld = [&](int i) AIM_AI -> V { return lds[i * B + b]; };
+      auto st = [&](int i, V x) AIM_AI {
+        if constexpr (last) {
+          if (i < n_x) bstore(x, fr, o_beta, t0 + (uint32_t)((i - beta) * es) * SV);
+        } else {
+          lds[i * B + b] = x;
+        }
+      };
+      V v[R];
+      if (active) stage_load<R, true, V>(v, beta, Mp, ld);
+      if constexpr (!last) __syncthreads();
+      if (active)
+        stage_compute_store_p<R, true, false, (last && HALF) ? R / 2 : R, last>(
+            v, beta, L, Mp, last ? twr : twl, st);
+      if constexpr (!last) __syncthreads();
+    });
   }
 }
 
@@ -355,12 +480,22 @@ void launch_mid(cx<T> *data, int n_x, int nfield, int Py, int Pz, int Hy, int Hz
                 const cx<T> *ghat, const cx<T> *tw, int blk, int64_t fstride, hipStream_t s) {
   constexpr int B = tile_mid<T, PC>();
   constexpr int threads = threads_mid<T, PC>();
+  if (PC::r(0) % 2 == 0 && 2 * n_x > PC::P)  // the half-pruned first/last stages need it
+    throw Error(AIM_ERR_ARG, "x pass: more than P/2 sources on a line");
+  if (blk <= 0 || blk % B != 0) throw Error(AIM_ERR_ARG, "x pass: tile does not divide the kz block");
+  // 32-bit buffer offsets: one kz block of a field, and the octant
+  if ((uint64_t)n_x * Py * blk * sizeof(cx<T>) >= (1ull << 31) ||
+      (uint64_t)Hy * Hz * (PC::P / 2 + 1) * sizeof(cx<T>) >= (1ull << 31))
+    throw Error(AIM_ERR_ARG, "x pass: grid too large for 32-bit offsets");
   const int ntile = (Pz + B - 1) / B;
-  const size_t lds = (size_t)PC::P * ((PC::ns > 1 ? B : 0) + 1) * sizeof(cx<T>);
-  const int64_t tiles = ((int64_t)Py * ntile + kXcd - 1) / kXcd * kXcd;
-  const int64_t blocks = tiles * nfield;
-  hipLaunchKernelGGL((k_fft_mid<T, PC>), dim3((unsigned)blocks), dim3(threads), lds, s, data, n_x,
-                     nfield, Py, Pz, ntile, Hy, Hz, ghat, tw, B, blk, fstride);
+  const size_t lds = (size_t)MidLds<T, PC>::total * sizeof(cx<T>);
+  // work items (fky, kz tile, mirror, field), fky = 0 .. Py/2, dealt to the
+  // XCDs in 8 contiguous ranges
+  const int64_t items = 2 * ((int64_t)Py / 2 + 1) * ntile * nfield;
+  const int64_t slots = (items + kXcd - 1) / kXcd;
+  if (slots * kXcd > INT32_MAX) throw Error(AIM_ERR_ARG, "x pass: too many tiles");
+  hipLaunchKernelGGL((k_fft_mid<T, PC>), dim3((unsigned)(slots * kXcd)), dim3(threads), lds, s,
+                     data, n_x, nfield, Py, Pz, ntile, (int)slots, Hy, Hz, ghat, tw, blk, fstride);
   LAUNCHCHECK();
 }
 
