@@ -9,7 +9,8 @@
 //     x[(j + L p) M' + k'],                p = 0..r-1.
 // The first stage (L = 1) reads plain strided input; the last (M' = 1) writes
 // natural order. Small DFTs are unrolled at compile time: primes 2, 3, 5, 7
-// directly, composite radices as two smaller DFTs with compile-time twiddles.
+// directly, composite radices as two smaller DFTs (prime-factor split for
+// coprime factors, else with compile-time twiddles).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -200,45 +201,124 @@ struct Dft<5, INV, V> : DftOddPrime<5, INV, V> {};
 template <bool INV, typename V>
 struct Dft<7, INV, V> : DftOddPrime<7, INV, V> {};
 
-// composite R = A * B, A the smallest prime factor: stage 1 runs B DFTs of
-// length A (L = 1, M' = B), stage 2 runs A DFTs of length B (L = A, M' = 1)
+constexpr int prime_power_part(int n, int p) {
+  int q = 1;
+  while (n % p == 0) {
+    n /= p;
+    q *= p;
+  }
+  return q;
+}
+constexpr int inverse_mod(int a, int m) {  // a^-1 mod m for coprime a, m (m > 1)
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 0;
+}
+
+// composite R. With N1 the power of R's smallest prime and N2 = R / N1:
+//  * N2 > 1 (coprime factors): prime-factor (Good-Thomas) split. Input n =
+//    (N2 n1 + N1 n2) mod R, N2 DFTs of length N1 over n1, then N1 DFTs of
+//    length N2 over n2; output k = (N2 t1 k1 + N1 t2 k2) mod R with
+//    t1 = N2^-1 mod N1, t2 = N1^-1 mod N2 (Chinese remainder indexing). The
+//    cross terms of n k are multiples of R, so no twiddles are needed
+//    between the layers.
+//  * N2 = 1 (prime power): Cooley-Tukey split A * B, A the prime: stage 1
+//    runs B DFTs of length A (L = 1, M' = B), stage 2 runs A DFTs of length
+//    B (L = A, M' = 1) after compile-time twiddles.
 template <int R, bool INV, typename V>
 struct Dft<R, INV, V, std::enable_if_t<(R > 3 && smallest_factor(R) != R)>> {
+  static constexpr int p = smallest_factor(R);
+  static constexpr int N1 = prime_power_part(R, p);
+  static constexpr int N2 = R / N1;
+
   __host__ __device__ __forceinline__ static void run(V *v) {
-    constexpr int A = smallest_factor(R);
-    constexpr int B = R / A;
-    V u[R];
-    static_for<B>([&](auto kp_) AIM_AI {
-      constexpr int kp = decltype(kp_)::value;
-      V s[A];
-      static_for<A>([&](auto q_) AIM_AI { s[decltype(q_)::value] = v[decltype(q_)::value * B + kp]; });
-      Dft<A, INV, V>::run(s);
-      static_for<A>([&](auto p_) AIM_AI { u[decltype(p_)::value * B + kp] = s[decltype(p_)::value]; });
-    });
-    static_for<A>([&](auto j_) AIM_AI {
-      constexpr int j = decltype(j_)::value;
-      V s[B];
-      static_for<B>([&](auto q_) AIM_AI {
-        constexpr int q = decltype(q_)::value;
-        s[q] = twc<R, j * q, INV>(u[j * B + q]);
+    if constexpr (N2 > 1) {
+      constexpr int t1 = inverse_mod(N2 % N1, N1), t2 = inverse_mod(N1 % N2, N2);
+      V a[N1 * N2];  // a[k1 N2 + n2]
+      static_for<N2>([&](auto n2_) AIM_AI {
+        constexpr int n2 = decltype(n2_)::value;
+        V s[N1];
+        static_for<N1>([&](auto n1_) AIM_AI {
+          constexpr int n1 = decltype(n1_)::value;
+          s[n1] = v[(N2 * n1 + N1 * n2) % R];
+        });
+        Dft<N1, INV, V>::run(s);
+        static_for<N1>([&](auto k1_) AIM_AI { a[decltype(k1_)::value * N2 + n2] = s[decltype(k1_)::value]; });
       });
-      Dft<B, INV, V>::run(s);
-      static_for<B>([&](auto p_) AIM_AI { v[j + A * decltype(p_)::value] = s[decltype(p_)::value]; });
-    });
+      static_for<N1>([&](auto k1_) AIM_AI {
+        constexpr int k1 = decltype(k1_)::value;
+        V s[N2];
+        static_for<N2>([&](auto n2_) AIM_AI { s[decltype(n2_)::value] = a[k1 * N2 + decltype(n2_)::value]; });
+        Dft<N2, INV, V>::run(s);
+        static_for<N2>([&](auto k2_) AIM_AI {
+          constexpr int k2 = decltype(k2_)::value;
+          v[(N2 * t1 * k1 + N1 * t2 * k2) % R] = s[k2];
+        });
+      });
+    } else {
+      constexpr int A = p;
+      constexpr int B = R / A;
+      V u[R];
+      static_for<B>([&](auto kp_) AIM_AI {
+        constexpr int kp = decltype(kp_)::value;
+        V s[A];
+        static_for<A>([&](auto q_) AIM_AI { s[decltype(q_)::value] = v[decltype(q_)::value * B + kp]; });
+        Dft<A, INV, V>::run(s);
+        static_for<A>([&](auto p_) AIM_AI { u[decltype(p_)::value * B + kp] = s[decltype(p_)::value]; });
+      });
+      static_for<A>([&](auto j_) AIM_AI {
+        constexpr int j = decltype(j_)::value;
+        V s[B];
+        static_for<B>([&](auto q_) AIM_AI {
+          constexpr int q = decltype(q_)::value;
+          s[q] = twc<R, j * q, INV>(u[j * B + q]);
+        });
+        Dft<B, INV, V>::run(s);
+        static_for<B>([&](auto p_) AIM_AI { v[j + A * decltype(p_)::value] = s[decltype(p_)::value]; });
+      });
+    }
   }
 };
 
 // Length-R DFT (R even) of a vector whose upper half v[R/2..R-1] is zero and
-// is not read: the first radix-2 layer of the composite split degenerates to
-// copies, leaving the two half-length DFTs of v and of v twisted by
-// exp(-+ 2 pi i q / R). Outputs in natural order as Dft<R>::run.
+// is not read. Outputs in natural order as Dft<R>::run.
+//  * R = 2 * odd: prime-factor split with N1 = 2. Each length-2 DFT pairs
+//    inputs n and n + R/2, exactly one of which lies in the lower half, so
+//    the layer reduces to copies and sign changes, leaving two DFTs of
+//    length R/2.
+//  * R divisible by 4: the radix-2 first layer of the Cooley-Tukey split
+//    degenerates to copies, leaving the two half-length DFTs of v and of v
+//    twisted by exp(-+ 2 pi i q / R).
 template <int R, bool INV, typename V>
 __host__ __device__ __forceinline__ void dft_upper_zero(V *v) {
   static_assert(R % 2 == 0, "upper-half-zero DFT needs an even length");
+  constexpr int B = R / 2;
   if constexpr (R == 2) {
     v[1] = v[0];
+  } else if constexpr (B % 2 == 1) {
+    constexpr int t2 = inverse_mod(2 % B, B);
+    V e[B], o[B];
+    static_for<B>([&](auto n2_) AIM_AI {
+      constexpr int n2 = decltype(n2_)::value;
+      constexpr int i0 = (2 * n2) % R;  // n1 = 0; n1 = 1 is i0 + B mod R
+      if constexpr (i0 < B) {           // (x_i0 + 0, x_i0 - 0)
+        e[n2] = v[i0];
+        o[n2] = v[i0];
+      } else {                          // (0 + x_i1, 0 - x_i1)
+        constexpr int i1 = (B + 2 * n2) % R;
+        e[n2] = v[i1];
+        o[n2] = mk<V>(-v[i1].x, -v[i1].y);
+      }
+    });
+    Dft<B, INV, V>::run(e);
+    Dft<B, INV, V>::run(o);
+    // k = (B t1 k1 + 2 t2 k2) mod R with t1 = B^-1 mod 2 = 1
+    static_for<B>([&](auto k2_) AIM_AI {
+      constexpr int k2 = decltype(k2_)::value;
+      v[(2 * t2 * k2) % R] = e[k2];
+      v[(B + 2 * t2 * k2) % R] = o[k2];
+    });
   } else {
-    constexpr int B = R / 2;
     V e[B], o[B];
     static_for<B>([&](auto q_) AIM_AI {
       constexpr int q = decltype(q_)::value;
