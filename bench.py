@@ -16,9 +16,12 @@ timed on a bounded sample on the host for reference.
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -31,12 +34,96 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "AIM matvec/s + % HBM roofline, mixed vs FP64 at equal RCS err (sphere 8λ)"
 STAGES = ["projection", "fwd_z", "fwd_y", "x_green", "inv_y", "inv_z", "interp_near"]
-KERNELS = ["k_anterp_fftz", "k_fft_contig", "k_fft_strided", "k_fft_mid", "k_fft_strided",
-           "k_fft_contig", "k_interp_near"]
+# kernel of each stage on the mixed path (the projection's depends on the tuned variant)
+KERNELS = [None, "k_fft_contig<float, false", "k_fft_strided<float, false", "k_fft_mid<float",
+           "k_fft_strided<float, true", "k_fft_contig<float, true", "k_interp_near<float"]
+
+
+def stage_kernel(d, fused):
+    if d == 0:
+        return "k_anterp_fftz<float" if fused else "k_anterp_gather<float"
+    return KERNELS[d]
+
+
+CSRC = os.path.join(ROOT, "paper_1010_1456_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+CAL_BYTES = 256 << 20  # the --calibrate kernel reads and writes 256 MiB per launch
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def sources_digest():
+    """Digest of the kernel sources: HBM counters taken on other sources are stale."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".h", ".hip", ".cpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def short_kernel(name):
+    name = name.replace("(anonymous namespace)::", "").split("(")[0]
+    name = re.sub(r"^void |aim::|fftk::", "", name)
+    name = re.sub(r"HIP_vector_type<(\w+), 2u>", r"\1", name)
+    name = re.sub(r"vec2_of<(\w+)>::type", r"\1", name)
+    return name.strip()
+
+
+def ingest_pmc(fetch_csv, write_csv, workload):
+    """Per-kernel HBM bytes per dispatch from a FETCH_SIZE run and a WRITE_SIZE
+    run of `bench.py --calibrate`: each counter is scaled by what it reads for
+    the calibration kernel (a plain elementwise multiply that reads 256 MiB
+    and writes 256 MiB). Writes profiles/<workload>_kernel_traffic.json."""
+    def load(path):
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            acc.setdefault(short_kernel(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+        return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
+
+    fetch, nf = load(fetch_csv)
+    write, _ = load(write_csv)
+    cal = [k for k in fetch if "MulFunctor" in k]
+    if not cal:
+        raise SystemExit("no calibration kernel in the counter runs (run bench.py with --calibrate)")
+    fs = CAL_BYTES / (fetch[cal[0]] * 1024.0)
+    ws = CAL_BYTES / (write[cal[0]] * 1024.0)
+    kernels = {}
+    for k, f in fetch.items():
+        if not k.startswith("k_"):
+            continue
+        w = write.get(k, 0.0)
+        kernels[k] = {"dispatches": nf[k], "fetch_kib": f, "write_kib": w,
+                      "read_bytes": f * 1024.0 * fs, "write_bytes": w * 1024.0 * ws,
+                      "bytes": (f * fs + w * ws) * 1024.0}
+    out = {"workload": workload, "sources_sha256": sources_digest(),
+           "fetch_scale": fs, "write_scale": ws,
+           "calibration": f"{cal[0]}: reads and writes {CAL_BYTES} bytes per launch",
+           "counters": [os.path.basename(fetch_csv), os.path.basename(write_csv)],
+           "kernels": kernels}
+    path = os.path.join(PROFILES, f"{workload}_kernel_traffic.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    print(f"wrote {path}: FETCH_SIZE x {fs:.3f}, WRITE_SIZE x {ws:.3f}")
+    for k, v in sorted(kernels.items()):
+        print(f"  {k}: read {v['read_bytes'] / 1e6:.1f} MB, write {v['write_bytes'] / 1e6:.1f} MB")
+
+
+def measured_traffic(workload, kernel_prefix):
+    """HBM bytes per launch of the kernel from the committed counter summary, or
+    None when there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(PROFILES, f"{workload}_kernel_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("sources_sha256") != sources_digest():
+        return None
+    hits = [v for k, v in t["kernels"].items() if k.startswith(kernel_prefix)]
+    return float(hits[0]["bytes"]) if len(hits) == 1 else None
 
 
 def stage_bytes(info, mesh, nrhs, s_grid, s_real, s_x, s_y, path):
@@ -171,7 +258,14 @@ def main(argv=None):
     ap.add_argument("--calibrate", action="store_true",
                     help="first run a plain elementwise copy of 256 MiB (3 launches) whose "
                          "FETCH_SIZE/WRITE_SIZE counters calibrate the HBM byte counts")
+    ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn the counter_collection.csv of a FETCH_SIZE and a WRITE_SIZE "
+                         "rocprofv3 run of `bench.py --calibrate` into "
+                         "profiles/<workload>_kernel_traffic.json, then exit")
     args = ap.parse_args(argv)
+    if args.ingest_pmc:
+        ingest_pmc(args.ingest_pmc[0], args.ingest_pmc[1], args.workload)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -217,6 +311,7 @@ def main(argv=None):
             + ",".join(f"{v:.3f}" for v in st_ms))
 
     mx = res["mixed"]
+    fused = bool(info["fused_projection"][0][1])
     ms_per_step = mx["wall"] / args.steps * 1e3
     value = R * args.steps / mx["wall"]
     d = int(np.argmax(mx["stage_ms"]))
@@ -250,13 +345,12 @@ def main(argv=None):
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": (("k_anterp_fftz" if info["fused_projection"][0][1] else "k_anterp_gather")
-                       if d == 0 else KERNELS[d]) + f" ({STAGES[d]})",
+            "kernel": stage_kernel(d, fused) + f"> ({STAGES[d]})",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(args.workload, stage_kernel(d, fused)),
             "algorithmic_bytes_per_launch": float(mx["bytes"][d]),
             "avg_launch_ms": float(mx["stage_ms"][d]),
         },
