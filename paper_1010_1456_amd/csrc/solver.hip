@@ -20,11 +20,6 @@ namespace {
 
 constexpr int kRed = 256;
 
-__device__ inline void atomic_add2(double2 *p, double a, double b) {
-  unsafeAtomicAdd(&p->x, a);
-  unsafeAtomicAdd(&p->y, b);
-}
-
 __device__ inline double2 block_sum2(double a, double b) {
   __shared__ double sa[kRed / 64], sb[kRed / 64];
   for (int off = 32; off > 0; off >>= 1) {
@@ -48,15 +43,19 @@ __device__ inline double2 block_sum2(double a, double b) {
 
 // All nv dot products of one Gram-Schmidt pass in one launch: every thread
 // keeps its kRows entries of w in registers and walks a group of kGroup basis
-// vectors (blockIdx.z); h[i*S + s] += sum_rows conj(V[i][r][row]) w[r][row]
-// via one atomic per wave.
-constexpr int kRows = 4;
+// vectors (blockIdx.z); each wave writes its partial sum of conj(V[i][r][row])
+// w[r][row] to part[(i S + s) np_stride + p], p = the wave's index, and
+// k_part_reduce adds the partials in a fixed order: no atomics, bitwise
+// reproducible.
+constexpr int kRows = 8;
 constexpr int kGroup = 8;
-__global__ void __launch_bounds__(256)
-    k_dots_all(const double2 *V, const double2 *w, int64_t ld, int64_t vstride, int64_t lo,
-               int64_t hi, int nv, int sys0, int S, double2 *h) {
+constexpr int kDotWaves = 4;  // waves per work-group of k_dots_part
+__global__ void __launch_bounds__(64 * kDotWaves)
+    k_dots_part(const double2 *V, const double2 *w, int64_t ld, int64_t vstride, int64_t lo,
+                int64_t hi, int nv, int sys0, int S, int64_t np_stride, double2 *part) {
   const int r = blockIdx.y;
   const int lane = threadIdx.x & 63;
+  const int64_t p = (int64_t)blockIdx.x * kDotWaves + (threadIdx.x >> 6);
   double2 wv[kRows];
   int64_t idx[kRows];
 #pragma unroll
@@ -71,17 +70,37 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
       if (idx[k] < hi) {
-        const double2 p = v[idx[k]];
-        a += p.x * wv[k].x + p.y * wv[k].y;
-        b += p.x * wv[k].y - p.y * wv[k].x;
+        const double2 q = v[idx[k]];
+        a += q.x * wv[k].x + q.y * wv[k].y;
+        b += q.x * wv[k].y - q.y * wv[k].x;
       }
     }
     for (int off = 32; off > 0; off >>= 1) {
       a += __shfl_xor(a, off, 64);
       b += __shfl_xor(b, off, 64);
     }
-    if (lane == 0) atomic_add2(&h[(int64_t)i * S + sys0 + r], a, b);
+    if (lane == 0) part[((int64_t)i * S + sys0 + r) * np_stride + p] = make_double2(a, b);
   }
+}
+// partials per work-group of k_dots_part over n rows
+int64_t dot_parts(int64_t n) { return (n + 64 * kDotWaves * kRows - 1) / (64 * kDotWaves * kRows) * kDotWaves; }
+
+// out[i S + s] = sum_{p < np} part[(i S + s) np_stride + p], fixed order;
+// one wave per (i, s): blockIdx.x = i, blockIdx.y = s - sys0
+__global__ void __launch_bounds__(64)
+    k_part_reduce(const double2 *part, int64_t np_stride, int np, int sys0, int S, double2 *out) {
+  const int64_t row = (int64_t)blockIdx.x * S + sys0 + blockIdx.y;
+  const double2 *pp = part + row * np_stride;
+  double a = 0, b = 0;
+  for (int q = threadIdx.x; q < np; q += 64) {
+    a += pp[q].x;
+    b += pp[q].y;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off, 64);
+    b += __shfl_xor(b, off, 64);
+  }
+  if (threadIdx.x == 0) out[row] = make_double2(a, b);
 }
 
 // w[r][row] -= sum_{i<nv} h[i*S + s] V[i][r][row]
@@ -100,9 +119,11 @@ __global__ void k_sub_basis(const double2 *V, double2 *w, int64_t ld, int64_t vs
   w[(int64_t)r * ld + n] = acc;
 }
 
-// nrm[s] += sum |w|^2 over the rows of system s
+// part[s kNormParts + blockIdx.x] = sum |w|^2 over the block's rows of system
+// s (grid-stride); k_norm_reduce adds the partials in a fixed order
+constexpr int kNormParts = 1024;  // upper bound of the grid's x extent
 __global__ void __launch_bounds__(kRed)
-    k_norm2(const double2 *w, int64_t ld, int64_t lo, int64_t hi, int sys0, double *nrm) {
+    k_norm2_part(const double2 *w, int64_t ld, int64_t lo, int64_t hi, int sys0, double *part) {
   const int r = blockIdx.y;
   double a = 0;
   for (int64_t n = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < hi;
@@ -111,7 +132,15 @@ __global__ void __launch_bounds__(kRed)
     a += p.x * p.x + p.y * p.y;
   }
   const double2 t = block_sum2(a, 0.0);
-  if (threadIdx.x == 0) unsafeAtomicAdd(&nrm[sys0 + r], t.x);
+  if (threadIdx.x == 0) part[(int64_t)(sys0 + r) * kNormParts + blockIdx.x] = t.x;
+}
+__global__ void __launch_bounds__(64)
+    k_norm_reduce(const double *part, int np, int sys0, double *nrm) {
+  const int s = sys0 + blockIdx.x;
+  double a = 0;
+  for (int q = threadIdx.x; q < np; q += 64) a += part[(int64_t)s * kNormParts + q];
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+  if (threadIdx.x == 0) nrm[s] = a;
 }
 
 // out[r][row] = w[r][row] / sqrt(nrm[s]) (0 if nrm == 0)
@@ -183,7 +212,9 @@ __global__ void k_inv_diag(const double2 *zd, double2 *dinv, int64_t n) {
 }
 
 unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
-unsigned red_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (n + kRed - 1) / kRed)); }
+unsigned red_blocks(int64_t n) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(kNormParts, (n + kRed - 1) / kRed));
+}
 
 struct Ctx {
   Plan *pl;
@@ -204,18 +235,24 @@ void apply(Ctx &c, aim_precision prec, const double2 *x, double2 *y) {
   }
 }
 
-// per-system squared norms of v (host result)
-void norms(Ctx &c, const double2 *v, double *dscratch, std::vector<double> &out) {
-  HIPCHECK(hipMemsetAsync(dscratch, 0, sizeof(double) * c.S, c.s));
+// nrm[s] = |v_s|^2 for every system, on the device (partials, fixed order)
+void norms_dev(Ctx &c, const double2 *v, double *part, double *nrm) {
   int mi = 0;
   for (auto &md : c.pl->mesh) {
-    hipLaunchKernelGGL(k_norm2, dim3(red_blocks(md.hp.n), c.R), dim3(kRed), 0, c.s, v, c.ld,
-                       md.offset, md.offset + md.hp.n, mi * c.R, dscratch);
+    const unsigned nb = red_blocks(md.hp.n);
+    hipLaunchKernelGGL(k_norm2_part, dim3(nb, c.R), dim3(kRed), 0, c.s, v, c.ld, md.offset,
+                       md.offset + md.hp.n, mi * c.R, part);
+    LAUNCHCHECK();
+    hipLaunchKernelGGL(k_norm_reduce, dim3(c.R), dim3(64), 0, c.s, part, (int)nb, mi * c.R, nrm);
     LAUNCHCHECK();
     ++mi;
   }
+}
+// per-system squared norms of v (host result)
+void norms(Ctx &c, const double2 *v, double *part, double *nrm, std::vector<double> &out) {
+  norms_dev(c, v, part, nrm);
   out.resize(c.S);
-  HIPCHECK(hipMemcpyAsync(out.data(), dscratch, sizeof(double) * c.S, hipMemcpyDeviceToHost, c.s));
+  HIPCHECK(hipMemcpyAsync(out.data(), nrm, sizeof(double) * c.S, hipMemcpyDeviceToHost, c.s));
   HIPCHECK(hipStreamSynchronize(c.s));
 }
 
@@ -238,74 +275,99 @@ struct GmresDev {
   double *tol_abs;  // [S] stop when |g_{j+1}| <= tol_abs
 };
 
-// New Hessenberg column j of every active system: sum of the two Gram-Schmidt
-// passes and the norm; apply the previous rotations, form the new one, update
-// the residual estimate |g_{j+1}|.
-__global__ void k_givens(GmresDev d, const double2 *h1, const double2 *h2, const double *nrm, int j,
-                         int m, int S) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S || !d.active[s]) return;
+// New Hessenberg column j of every active system (one 64-lane work-group per
+// system): sum of the two Gram-Schmidt passes and the norm; apply the
+// previous rotations, form the new one, update the residual estimate
+// |g_{j+1}|. The column and the rotations are staged in LDS by all lanes; the
+// rotation chain itself is sequential. LDS: (3m + 1) complex values.
+__global__ void __launch_bounds__(64)
+    k_givens(GmresDev d, const double2 *h1, const double2 *h2, const double *nrm, int j, int m,
+             int S) {
+  const int s = blockIdx.x;
+  if (!d.active[s]) return;  // uniform over the work-group
+  extern __shared__ double2 gsh[];
+  double2 *col = gsh, *cl = gsh + (m + 1), *sl = cl + m;
   double2 *Hs = d.H + (int64_t)s * (m + 1) * m;
   double2 *cs = d.cs + (int64_t)s * m, *sn = d.sn + (int64_t)s * m;
-  double2 *g = d.g + (int64_t)s * (m + 1);
-  for (int i = 0; i <= j; ++i) {
+  for (int i = threadIdx.x; i <= j; i += 64) {
     const double2 a = h1[(int64_t)i * S + s], b = h2[(int64_t)i * S + s];
-    Hs[i * m + j] = make_double2(a.x + b.x, a.y + b.y);
+    col[i] = make_double2(a.x + b.x, a.y + b.y);
   }
-  double2 hj1 = make_double2(sqrt(nrm[s]), 0.0);
-  for (int i = 0; i < j; ++i) {
-    const double2 hi = Hs[i * m + j];
-    const double2 hn = Hs[(i + 1) * m + j];
-    // [hi; hn] <- [conj(c) hi + conj(s) hn; -s hi + c hn]
-    const double2 t0 = cconjmul_(cs[i], hi), t1 = cconjmul_(sn[i], hn);
-    const double2 u0 = cmul_(sn[i], hi), u1 = cmul_(cs[i], hn);
-    Hs[i * m + j] = make_double2(t0.x + t1.x, t0.y + t1.y);
-    Hs[(i + 1) * m + j] = make_double2(u1.x - u0.x, u1.y - u0.y);
+  for (int i = threadIdx.x; i < j; i += 64) {
+    cl[i] = cs[i];
+    sl[i] = sn[i];
   }
-  const double2 a = Hs[j * m + j];
-  const double den = sqrt(a.x * a.x + a.y * a.y + hj1.x * hj1.x);
-  double2 c, sv;
-  if (den == 0.0) {
-    c = make_double2(1.0, 0.0);
-    sv = make_double2(0.0, 0.0);
-  } else {
-    c = make_double2(a.x / den, a.y / den);
-    sv = make_double2(hj1.x / den, 0.0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2 *g = d.g + (int64_t)s * (m + 1);
+    const double2 hj1 = make_double2(sqrt(nrm[s]), 0.0);
+    for (int i = 0; i < j; ++i) {
+      const double2 hi = col[i], hn = col[i + 1];
+      // [hi; hn] <- [conj(c) hi + conj(s) hn; -s hi + c hn]
+      const double2 t0 = cconjmul_(cl[i], hi), t1 = cconjmul_(sl[i], hn);
+      const double2 u0 = cmul_(sl[i], hi), u1 = cmul_(cl[i], hn);
+      col[i] = make_double2(t0.x + t1.x, t0.y + t1.y);
+      col[i + 1] = make_double2(u1.x - u0.x, u1.y - u0.y);
+    }
+    const double2 a = col[j];
+    const double den = sqrt(a.x * a.x + a.y * a.y + hj1.x * hj1.x);
+    double2 c, sv;
+    if (den == 0.0) {
+      c = make_double2(1.0, 0.0);
+      sv = make_double2(0.0, 0.0);
+    } else {
+      c = make_double2(a.x / den, a.y / den);
+      sv = make_double2(hj1.x / den, 0.0);
+    }
+    cs[j] = c;
+    sn[j] = sv;
+    col[j] = make_double2(den, 0.0);
+    col[j + 1] = make_double2(0.0, 0.0);
+    const double2 gj = g[j];
+    const double2 gn = cmul_(sv, gj);
+    g[j + 1] = make_double2(-gn.x, -gn.y);
+    g[j] = cconjmul_(c, gj);
+    d.its[s] += 1;
+    d.jend[s] = j + 1;
+    const double res = sqrt(gn.x * gn.x + gn.y * gn.y);
+    if (res <= d.tol_abs[s] || den == 0.0) d.active[s] = 0;
   }
-  cs[j] = c;
-  sn[j] = sv;
-  Hs[j * m + j] = make_double2(den, 0.0);
-  Hs[(j + 1) * m + j] = make_double2(0.0, 0.0);
-  const double2 gj = g[j];
-  const double2 gn = cmul_(sv, gj);
-  g[j + 1] = make_double2(-gn.x, -gn.y);
-  g[j] = cconjmul_(c, gj);
-  d.its[s] += 1;
-  d.jend[s] = j + 1;
-  const double res = sqrt(gn.x * gn.x + gn.y * gn.y);
-  if (res <= d.tol_abs[s] || den == 0.0) d.active[s] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j + 1; i += 64) Hs[i * m + j] = col[i];
 }
 
-// y = H^-1 g on the jend x jend upper triangle (y stored [i][s] like h)
-__global__ void k_backsub(GmresDev d, double2 *y, int m, int S) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
+// y = H^-1 g on the jend x jend upper triangle (y stored [i][s] like h); one
+// 64-lane work-group per system: rows bottom-up, each row's sum over the
+// known y_k split over the lanes (fixed order). LDS: m complex values.
+__global__ void __launch_bounds__(64) k_backsub(GmresDev d, double2 *y, int m, int S) {
+  const int s = blockIdx.x;
+  extern __shared__ double2 ysh[];
   const int n = d.jend[s];
   const double2 *Hs = d.H + (int64_t)s * (m + 1) * m;
   const double2 *g = d.g + (int64_t)s * (m + 1);
   for (int i = n - 1; i >= 0; --i) {
-    double2 acc = g[i];
-    for (int k = i + 1; k < n; ++k) {
-      const double2 t = cmul_(Hs[i * m + k], y[(int64_t)k * S + s]);
-      acc.x -= t.x;
-      acc.y -= t.y;
+    double ax = 0, ay = 0;
+    for (int k = i + 1 + threadIdx.x; k < n; k += 64) {
+      const double2 t = cmul_(Hs[i * m + k], ysh[k]);
+      ax += t.x;
+      ay += t.y;
     }
-    const double2 hd = Hs[i * m + i];
-    const double dd = hd.x * hd.x + hd.y * hd.y;
-    y[(int64_t)i * S + s] = dd == 0.0 ? make_double2(0.0, 0.0)
-                                      : make_double2((acc.x * hd.x + acc.y * hd.y) / dd,
-                                                     (acc.y * hd.x - acc.x * hd.y) / dd);
+    for (int off = 32; off > 0; off >>= 1) {
+      ax += __shfl_xor(ax, off, 64);
+      ay += __shfl_xor(ay, off, 64);
+    }
+    if (threadIdx.x == 0) {
+      const double2 gi = g[i];
+      const double2 acc = make_double2(gi.x - ax, gi.y - ay);
+      const double2 hd = Hs[i * m + i];
+      const double dd = hd.x * hd.x + hd.y * hd.y;
+      ysh[i] = dd == 0.0 ? make_double2(0.0, 0.0)
+                         : make_double2((acc.x * hd.x + acc.y * hd.y) / dd,
+                                        (acc.y * hd.x - acc.x * hd.y) / dd);
+    }
+    __syncthreads();
   }
+  for (int i = threadIdx.x; i < n; i += 64) y[(int64_t)i * S + s] = ysh[i];
 }
 
 struct Work {
@@ -313,6 +375,9 @@ struct Work {
   double2 *z = nullptr, *w = nullptr;
   double2 *h1 = nullptr, *h2 = nullptr, *y = nullptr;
   double *nrm = nullptr;
+  double2 *part = nullptr;  // dot-product partials [(m+1) S][np_stride]
+  int64_t np_stride = 0;
+  double *npart = nullptr;  // norm partials [S][kNormParts]
   GmresDev dev{};
 };
 
@@ -348,7 +413,7 @@ int gmres_run(Ctx &c, aim_precision prec, Work &wk, int m, const double2 *rhs, d
       LAUNCHCHECK();
     }
     first_cycle = false;
-    norms(c, wk.w, wk.nrm, r2);
+    norms(c, wk.w, wk.npart, wk.nrm, r2);
     bool all = true;
     for (int s = 0; s < S; ++s) {
       if (!done[s] && r2[s] <= tol_s[s] * tol_s[s] * rhs_norm2[s]) done[s] = 1;
@@ -388,13 +453,15 @@ int gmres_run(Ctx &c, aim_precision prec, Work &wk, int m, const double2 *rhs, d
       // two passes of classical Gram-Schmidt
       for (int pass = 0; pass < 2; ++pass) {
         double2 *h = pass == 0 ? wk.h1 : wk.h2;
-        HIPCHECK(hipMemsetAsync(h, 0, sizeof(double2) * (j + 1) * S, c.s));
         int mi = 0;
         for (auto &md : c.pl->mesh) {
-          hipLaunchKernelGGL(k_dots_all, dim3(nblk(md.hp.n, 256 * kRows), R, nblk(j + 1, kGroup)),
-                             dim3(256), 0, c.s,
-                             wk.V, wk.w, ld, vstride, md.offset, md.offset + md.hp.n, j + 1, mi * R, S,
-                             h);
+          const int64_t nb = dot_parts(md.hp.n) / kDotWaves;
+          hipLaunchKernelGGL(k_dots_part, dim3((unsigned)nb, R, nblk(j + 1, kGroup)),
+                             dim3(64 * kDotWaves), 0, c.s, wk.V, wk.w, ld, vstride, md.offset,
+                             md.offset + md.hp.n, j + 1, mi * R, S, wk.np_stride, wk.part);
+          LAUNCHCHECK();
+          hipLaunchKernelGGL(k_part_reduce, dim3(j + 1, R), dim3(64), 0, c.s, wk.part,
+                             wk.np_stride, (int)(nb * kDotWaves), mi * R, S, h);
           LAUNCHCHECK();
           hipLaunchKernelGGL(k_sub_basis, dim3(nblk(md.hp.n, 256), R), dim3(256), 0, c.s, wk.V,
                              wk.w, ld, vstride, md.offset, md.offset + md.hp.n, j + 1, mi * R, S, h);
@@ -402,13 +469,10 @@ int gmres_run(Ctx &c, aim_precision prec, Work &wk, int m, const double2 *rhs, d
           ++mi;
         }
       }
-      HIPCHECK(hipMemsetAsync(wk.nrm, 0, sizeof(double) * S, c.s));
+      norms_dev(c, wk.w, wk.npart, wk.nrm);
       {
         int mi = 0;
         for (auto &md : c.pl->mesh) {
-          hipLaunchKernelGGL(k_norm2, dim3(red_blocks(md.hp.n), R), dim3(kRed), 0, c.s, wk.w, ld,
-                             md.offset, md.offset + md.hp.n, mi * R, wk.nrm);
-          LAUNCHCHECK();
           hipLaunchKernelGGL(k_normalize, dim3(nblk(md.hp.n, 256), R), dim3(256), 0, c.s, wk.w,
                              wk.V + (j + 1) * vstride, ld, md.offset, md.offset + md.hp.n, mi * R,
                              wk.nrm);
@@ -416,8 +480,8 @@ int gmres_run(Ctx &c, aim_precision prec, Work &wk, int m, const double2 *rhs, d
           ++mi;
         }
       }
-      hipLaunchKernelGGL(k_givens, dim3(nblk(S, 64)), dim3(64), 0, c.s, wk.dev, wk.h1, wk.h2, wk.nrm,
-                         j, m, S);
+      hipLaunchKernelGGL(k_givens, dim3(S), dim3(64), sizeof(double2) * (3 * (size_t)m + 1), c.s,
+                         wk.dev, wk.h1, wk.h2, wk.nrm, j, m, S);
       LAUNCHCHECK();
       if ((j + 1) % kCheckEvery == 0 || j == m - 1) {
         HIPCHECK(hipMemcpyAsync(act.data(), wk.dev.active, sizeof(int) * S, hipMemcpyDeviceToHost, c.s));
@@ -428,7 +492,8 @@ int gmres_run(Ctx &c, aim_precision prec, Work &wk, int m, const double2 *rhs, d
       }
     }
     // d += D^-1 V y, y = H^-1 g per system (systems done before the cycle: jend = 0)
-    hipLaunchKernelGGL(k_backsub, dim3(nblk(S, 64)), dim3(64), 0, c.s, wk.dev, wk.y, m, S);
+    hipLaunchKernelGGL(k_backsub, dim3(S), dim3(64), sizeof(double2) * (size_t)m, c.s, wk.dev,
+                       wk.y, m, S);
     LAUNCHCHECK();
     {
       int mi = 0;
@@ -473,6 +538,9 @@ aim_status gmres_solve(Plan *pl, aim_precision prec, int R, const aim_planewave 
     wk.h2 = (double2 *)alloc(sizeof(double2) * (size_t)(m + 1) * S);
     wk.y = (double2 *)alloc(sizeof(double2) * (size_t)(m + 1) * S);
     wk.nrm = (double *)alloc(sizeof(double) * S);
+    for (auto &md : pl->mesh) wk.np_stride = std::max(wk.np_stride, dot_parts(md.hp.n));
+    wk.part = (double2 *)alloc(sizeof(double2) * (size_t)(m + 1) * S * wk.np_stride);
+    wk.npart = (double *)alloc(sizeof(double) * (size_t)S * kNormParts);
     wk.dev.H = (double2 *)alloc(sizeof(double2) * (size_t)S * (m + 1) * m);
     wk.dev.cs = (double2 *)alloc(sizeof(double2) * (size_t)S * m);
     wk.dev.sn = (double2 *)alloc(sizeof(double2) * (size_t)S * m);
@@ -493,7 +561,7 @@ aim_status gmres_solve(Plan *pl, aim_precision prec, int R, const aim_planewave 
     }
     Ctx c{pl, s, R, S, ld, dinv};
     std::vector<double> b2, r2;
-    norms(c, b, wk.nrm, b2);
+    norms(c, b, wk.npart, wk.nrm, b2);
     if (!o.warm_start) HIPCHECK(hipMemsetAsync(x, 0, sizeof(double2) * cnt, s));
     std::vector<int> its(S, 0);
     int n_low = 0, n64 = 0, total = 0;
@@ -504,7 +572,7 @@ aim_status gmres_solve(Plan *pl, aim_precision prec, int R, const aim_planewave 
       ++n64;
       hipLaunchKernelGGL(k_residual, dim3(nblk(cnt, 256)), dim3(256), 0, s, b, r, cnt);
       LAUNCHCHECK();
-      norms(c, r, wk.nrm, r2);
+      norms(c, r, wk.npart, wk.nrm, r2);
     };
     if (prec == AIM_FP64) {
       if (o.warm_start) {
