@@ -59,44 +59,90 @@ __global__ void k_point_currents(const int32_t *tris, const double *verts, const
 }
 
 constexpr int kRcsThreads = 256;
-constexpr int kChunk = 256;
+constexpr int kDirTile = 8;      // directions per work-group
+constexpr int kPtsChunk = 4096;  // quadrature points per work-group
 
+// part[(rr ndir + d) nchunk + chunk] = sum over the chunk's points of
+// (theta_hat(d) . J) exp(+j k r_hat(d) . r)
 __global__ void __launch_bounds__(kRcsThreads)
-    k_rcs(const double *pos, const double2 *J, int64_t npts, const double *theta, int ntheta,
-          const double *phi, int nphi, double k, double scale, double *sigma) {
-  __shared__ double sp[kChunk * 3];
-  __shared__ double2 sj[kChunk * 3];
-  const int rr = blockIdx.y;
-  const int64_t dir = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool ok = dir < (int64_t)ntheta * nphi;
-  const int a = ok ? (int)(dir / nphi) : 0, b = ok ? (int)(dir % nphi) : 0;
-  double st, ct, sph, cph;
-  sincos(theta[a], &st, &ct);
-  sincos(phi[b], &sph, &cph);
-  const double rx = st * cph, ry = st * sph, rz = ct;
-  const double tx = ct * cph, ty = ct * sph, tz = -st;
-  const double2 *Jr = J + (int64_t)rr * npts * 3;
-  double nr = 0, ni = 0;
-  for (int64_t c0 = 0; c0 < npts; c0 += kChunk) {
-    const int cnt = (int)min<int64_t>(kChunk, npts - c0);
-    __syncthreads();
-    for (int i = threadIdx.x; i < cnt * 3; i += blockDim.x) {
-      sp[i] = pos[c0 * 3 + i];
-      sj[i] = Jr[c0 * 3 + i];
+    k_rcs_part(const double *pos, const double2 *J, int64_t npts, const double *theta, int ntheta,
+               const double *phi, int nphi, double k, int nchunk, double2 *part) {
+  __shared__ double dir[kDirTile][6];  // r_hat, theta_hat
+  __shared__ double red[kRcsThreads / 64][2 * kDirTile];
+  const int rr = blockIdx.z;
+  const int64_t ndir = (int64_t)ntheta * nphi;
+  const int64_t d0 = (int64_t)blockIdx.x * kDirTile;
+  if (threadIdx.x < kDirTile) {
+    const int64_t d = d0 + threadIdx.x;
+    double st = 0, ct = 1, sph = 0, cph = 1;
+    if (d < ndir) {
+      sincos(theta[d / nphi], &st, &ct);
+      sincos(phi[d % nphi], &sph, &cph);
     }
-    __syncthreads();
-    for (int i = 0; i < cnt; ++i) {
-      const double ph = k * (rx * sp[3 * i] + ry * sp[3 * i + 1] + rz * sp[3 * i + 2]);
+    double *o = dir[threadIdx.x];
+    o[0] = st * cph;
+    o[1] = st * sph;
+    o[2] = ct;
+    o[3] = ct * cph;
+    o[4] = ct * sph;
+    o[5] = -st;
+  }
+  __syncthreads();
+  double nr[kDirTile], ni[kDirTile];
+#pragma unroll
+  for (int q = 0; q < kDirTile; ++q) nr[q] = ni[q] = 0;
+  const double2 *Jr = J + (int64_t)rr * npts * 3;
+  const int64_t p0 = (int64_t)blockIdx.y * kPtsChunk;
+  const int64_t p1 = min(p0 + kPtsChunk, npts);
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += kRcsThreads) {
+    const double x = pos[3 * p], y = pos[3 * p + 1], z = pos[3 * p + 2];
+    const double2 jx = Jr[3 * p], jy = Jr[3 * p + 1], jz = Jr[3 * p + 2];
+#pragma unroll
+    for (int q = 0; q < kDirTile; ++q) {
+      const double *o = dir[q];
       double s, c;
-      sincos(ph, &s, &c);
-      // theta_hat . J
-      const double jr = tx * sj[3 * i].x + ty * sj[3 * i + 1].x + tz * sj[3 * i + 2].x;
-      const double ji = tx * sj[3 * i].y + ty * sj[3 * i + 1].y + tz * sj[3 * i + 2].y;
-      nr += jr * c - ji * s;
-      ni += jr * s + ji * c;
+      sincos(k * (o[0] * x + o[1] * y + o[2] * z), &s, &c);
+      const double jr = o[3] * jx.x + o[4] * jy.x + o[5] * jz.x;  // theta_hat . J
+      const double ji = o[3] * jx.y + o[4] * jy.y + o[5] * jz.y;
+      nr[q] += jr * c - ji * s;
+      ni[q] += jr * s + ji * c;
     }
   }
-  if (ok) sigma[(int64_t)rr * ntheta * nphi + dir] = scale * (nr * nr + ni * ni);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kDirTile; ++q) {
+    for (int off = 32; off > 0; off >>= 1) {
+      nr[q] += __shfl_xor(nr[q], off, 64);
+      ni[q] += __shfl_xor(ni[q], off, 64);
+    }
+    if (lane == 0) {
+      red[w][2 * q] = nr[q];
+      red[w][2 * q + 1] = ni[q];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kDirTile && d0 + threadIdx.x < ndir) {
+    double a = 0, b = 0;
+    for (int i = 0; i < kRcsThreads / 64; ++i) {
+      a += red[i][2 * threadIdx.x];
+      b += red[i][2 * threadIdx.x + 1];
+    }
+    part[((int64_t)rr * ndir + d0 + threadIdx.x) * nchunk + blockIdx.y] = make_double2(a, b);
+  }
+}
+
+// sigma[rr ndir + d] = scale |sum over chunks of part|^2 (chunks in order)
+__global__ void k_rcs_reduce(const double2 *part, int nchunk, int64_t count, double scale,
+                             double *sigma) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  double a = 0, b = 0;
+  for (int c = 0; c < nchunk; ++c) {
+    const double2 v = part[t * nchunk + c];
+    a += v.x;
+    b += v.y;
+  }
+  sigma[t] = scale * (a * a + b * b);
 }
 
 }  // namespace
@@ -137,9 +183,15 @@ void rcs_mesh(Plan *pl, MeshDev &md, int nrhs, const double2 *x, int64_t ldx, in
     LAUNCHCHECK();
     const double keta = h.k * kEta0;
     const double scale = keta * keta / (4.0 * kPi);
-    hipLaunchKernelGGL(k_rcs, dim3((unsigned)((ndir + kRcsThreads - 1) / kRcsThreads), nrhs),
-                       dim3(kRcsThreads), 0, s, pos, J, npts, dth, ntheta, dph, nphi, h.k, scale,
-                       dsig);
+    const int nchunk = (int)((npts + kPtsChunk - 1) / kPtsChunk);
+    double2 *part = (double2 *)alloc(sizeof(double2) * (size_t)ndir * nrhs * nchunk);
+    hipLaunchKernelGGL(k_rcs_part,
+                       dim3((unsigned)((ndir + kDirTile - 1) / kDirTile), (unsigned)nchunk, nrhs),
+                       dim3(kRcsThreads), 0, s, pos, J, npts, dth, ntheta, dph, nphi, h.k, nchunk,
+                       part);
+    LAUNCHCHECK();
+    hipLaunchKernelGGL(k_rcs_reduce, dim3((unsigned)((ndir * nrhs + 255) / 256)), dim3(256), 0, s,
+                       part, nchunk, ndir * nrhs, scale, dsig);
     LAUNCHCHECK();
     HIPCHECK(hipMemcpyAsync(sigma, dsig, sizeof(double) * ndir * nrhs, hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
