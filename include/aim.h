@@ -147,8 +147,15 @@ typedef struct {
   int32_t restart;
   int32_t max_iter;
   int32_t warm_start; /* 1: x_io holds the initial guess */
-  int32_t reserved;
+  int32_t flags;      /* AIM_SOLVE_* below */
 } aim_solve_opts;
+
+/* The Arnoldi steps between two convergence polls (8 iterations) are
+ * captured once into a HIP graph and replayed on later restart cycles and
+ * later solves of the same shape (right-hand sides, restart); results are
+ * bitwise those of direct launches. This flag launches every kernel
+ * directly instead. */
+#define AIM_SOLVE_NO_GRAPH 1
 
 /* Per right-hand side results of aim_gmres_solve. */
 typedef struct {

@@ -29,6 +29,7 @@ AIM_MIXED = 1
 AIM_MIXED_IO64 = 2
 AIM_NSTAGE = 7
 AIM_FLAG_NO_MIXED = 1
+AIM_SOLVE_NO_GRAPH = 1
 AIM_MAX_MESH = 16
 AIM_DATA_LAMBDA64 = 1
 AIM_DATA_NEAR64 = 2
@@ -82,7 +83,7 @@ class AimInfo(ctypes.Structure):
 
 class AimSolveOpts(ctypes.Structure):
     _fields_ = [("tol", c_double), ("restart", c_int32), ("max_iter", c_int32),
-                ("warm_start", c_int32), ("reserved", c_int32)]
+                ("warm_start", c_int32), ("flags", c_int32)]
 
 
 class AimSolveStats(ctypes.Structure):
@@ -311,7 +312,7 @@ class Plan:
         return b
 
     def solve(self, waves, precision=AIM_MIXED, tol=1e-4, restart=100, max_iter=5000, x0=None,
-              stream=None, raise_on_noconv=True):
+              stream=None, raise_on_noconv=True, graphs=True):
         torch = self._torch
         arr = _waves(waves)
         R = len(waves)
@@ -319,7 +320,8 @@ class Plan:
             x = x0.to(torch.complex128).reshape(R, self.n_total).contiguous().clone()
         else:
             x = torch.zeros((R, self.n_total), dtype=torch.complex128, device="cuda")
-        opts = AimSolveOpts(float(tol), int(restart), int(max_iter), 1 if x0 is not None else 0, 0)
+        opts = AimSolveOpts(float(tol), int(restart), int(max_iter), 1 if x0 is not None else 0,
+                            0 if graphs else AIM_SOLVE_NO_GRAPH)
         st = (AimSolveStats * R)()
         status = lib().aim_gmres_solve(self._h, precision, R, arr, ctypes.byref(opts),
                                        c_void_p(x.data_ptr()), st, self._stream(stream))

@@ -150,10 +150,12 @@ struct Plan {
   // grid work buffers (per precision), grown on demand
   void *work[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
   size_t work_bytes[2][3] = {{0, 0, 0}, {0, 0, 0}};
-  // solver scratch
-  void *solver_buf = nullptr;
-  size_t solver_bytes = 0;
+  uint64_t work_gen = 0;  // bumped whenever a grid work buffer moves (invalidates solve graphs)
+  // solver buffers, stream and captured graphs, kept across solves (solver.hip)
+  struct SolverState *solver = nullptr;
 };
+// releases the solver state (graphs, stream, buffers) of a plan
+void solver_release(Plan *pl);
 
 // set-up kernels (setup_kernels.hip)
 void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s);

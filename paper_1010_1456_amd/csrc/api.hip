@@ -215,6 +215,7 @@ aim_status aim_plan_info(const aim_plan *plan, aim_info *out) {
 
 void aim_destroy(aim_plan *plan) {
   if (!plan) return;
+  solver_release(plan);
   free_all(plan);
   delete plan;
 }

@@ -217,6 +217,7 @@ void *work_buffer(Plan *pl, int prec, int which, size_t bytes) {
     pl->work_bytes[prec][which] = 0;
     pl->work[prec][which] = dev_alloc(pl, bytes);
     pl->work_bytes[prec][which] = bytes;
+    ++pl->work_gen;
   }
   return pl->work[prec][which];
 }

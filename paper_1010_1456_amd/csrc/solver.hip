@@ -5,12 +5,18 @@
 // system; all systems advance in lock-step so one batched AIM product serves
 // them all. Arnoldi runs in FP64 on the device (classical Gram-Schmidt, two
 // passes), and so do the Givens rotations and the residual estimate; the host
-// only polls the per-system active flags every few iterations. For AIM_MIXED the
+// only polls the per-system active flags every few iterations. The steps
+// between two polls are captured once into a HIP graph and replayed (the
+// launch sequence of a segment depends only on its step range, the precision
+// and the buffers, which persist in the plan across solves). For AIM_MIXED the
 // inner solves use the c64 operator on c128 Krylov vectors, inside an FP64
 // iterative-refinement loop r = b - A64 x that decides convergence.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <map>
+#include <tuple>
 
 #include "aim_internal.h"
 
@@ -383,16 +389,163 @@ struct Work {
 
 constexpr int kCheckEvery = 8;  // iterations between convergence checks on the host
 
+}  // namespace
+
+// Buffers, stream and captured graphs of the solver, kept in the plan for
+// the shape (right-hand sides per mesh R, restart m) of the last solve.
+struct SolverState {
+  int R = 0, m = 0;
+  Work wk;
+  double2 *dinv = nullptr;  // Jacobi: 1 / diag(Z^MOM)
+  std::vector<void *> bufs;
+  hipStream_t stream = nullptr;
+  hipEvent_t entry = nullptr;
+  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;  // (precision, j0, j1)
+  uint64_t gen = 0;       // plan work-buffer generation the graphs were captured with
+  bool warm[2] = {false, false};  // a direct step of this precision ran on these buffers
+};
+
+namespace {
+
+void drop_graphs(SolverState &st) {
+  for (auto &g : st.graphs) (void)hipGraphExecDestroy(g.second);
+  st.graphs.clear();
+}
+
+SolverState &solver_state(Plan *pl, int R, int m) {
+  if (!pl->solver) pl->solver = new SolverState();
+  SolverState &st = *pl->solver;
+  if (!st.stream) {
+    HIPCHECK(hipStreamCreateWithFlags(&st.stream, hipStreamNonBlocking));
+    HIPCHECK(hipEventCreateWithFlags(&st.entry, hipEventDisableTiming));
+  }
+  if (st.R == R && st.m == m) return st;
+  HIPCHECK(hipStreamSynchronize(st.stream));
+  drop_graphs(st);
+  for (void *p : st.bufs) dev_free(pl, p);
+  st.bufs.clear();
+  st.R = st.m = 0;
+  st.warm[0] = st.warm[1] = false;
+  auto alloc = [&](size_t bytes) {
+    void *p = dev_alloc(pl, bytes);
+    st.bufs.push_back(p);
+    return p;
+  };
+  const int S = pl->nmesh * R;
+  const int64_t ld = pl->n_total, cnt = (int64_t)R * ld;
+  Work &wk = st.wk;
+  wk.V = (double2 *)alloc(sizeof(double2) * (size_t)(m + 1) * cnt);
+  wk.z = (double2 *)alloc(sizeof(double2) * cnt);
+  wk.w = (double2 *)alloc(sizeof(double2) * cnt);
+  wk.h1 = (double2 *)alloc(sizeof(double2) * (size_t)(m + 1) * S);
+  wk.h2 = (double2 *)alloc(sizeof(double2) * (size_t)(m + 1) * S);
+  wk.y = (double2 *)alloc(sizeof(double2) * (size_t)(m + 1) * S);
+  wk.nrm = (double *)alloc(sizeof(double) * S);
+  wk.np_stride = 0;
+  for (auto &md : pl->mesh) wk.np_stride = std::max(wk.np_stride, dot_parts(md.hp.n));
+  wk.part = (double2 *)alloc(sizeof(double2) * (size_t)(m + 1) * S * wk.np_stride);
+  wk.npart = (double *)alloc(sizeof(double) * (size_t)S * kNormParts);
+  wk.dev.H = (double2 *)alloc(sizeof(double2) * (size_t)S * (m + 1) * m);
+  wk.dev.cs = (double2 *)alloc(sizeof(double2) * (size_t)S * m);
+  wk.dev.sn = (double2 *)alloc(sizeof(double2) * (size_t)S * m);
+  wk.dev.g = (double2 *)alloc(sizeof(double2) * (size_t)S * (m + 1));
+  wk.dev.active = (int *)alloc(sizeof(int) * S);
+  wk.dev.its = (int *)alloc(sizeof(int) * S);
+  wk.dev.jend = (int *)alloc(sizeof(int) * S);
+  wk.dev.tol_abs = (double *)alloc(sizeof(double) * S);
+  st.dinv = (double2 *)alloc(sizeof(double2) * ld);
+  for (auto &md : pl->mesh) {
+    hipLaunchKernelGGL(k_inv_diag, dim3(nblk(md.hp.n, 256)), dim3(256), 0, st.stream, md.zdiag,
+                       st.dinv + md.offset, md.hp.n);
+    LAUNCHCHECK();
+  }
+  st.R = R;
+  st.m = m;
+  return st;
+}
+
+// One Arnoldi step j of every system: w = A D^-1 V[j], two classical
+// Gram-Schmidt passes, V[j+1] = w / |w|, Hessenberg column j and rotation.
+void arnoldi_step(Ctx &c, aim_precision prec, Work &wk, int j, int m) {
+  const int S = c.S, R = c.R;
+  const int64_t ld = c.ld, vstride = (int64_t)R * ld;
+  hipLaunchKernelGGL(k_precond, dim3(nblk(ld, 256)), dim3(256), 0, c.s, wk.V + j * vstride, wk.z,
+                     c.dinv, ld, R);
+  LAUNCHCHECK();
+  apply(c, prec, wk.z, wk.w);
+  for (int pass = 0; pass < 2; ++pass) {
+    double2 *h = pass == 0 ? wk.h1 : wk.h2;
+    int mi = 0;
+    for (auto &md : c.pl->mesh) {
+      const int64_t nb = dot_parts(md.hp.n) / kDotWaves;
+      hipLaunchKernelGGL(k_dots_part, dim3((unsigned)nb, R, nblk(j + 1, kGroup)),
+                         dim3(64 * kDotWaves), 0, c.s, wk.V, wk.w, ld, vstride, md.offset,
+                         md.offset + md.hp.n, j + 1, mi * R, S, wk.np_stride, wk.part);
+      LAUNCHCHECK();
+      hipLaunchKernelGGL(k_part_reduce, dim3(j + 1, R), dim3(64), 0, c.s, wk.part, wk.np_stride,
+                         (int)(nb * kDotWaves), mi * R, S, h);
+      LAUNCHCHECK();
+      hipLaunchKernelGGL(k_sub_basis, dim3(nblk(md.hp.n, 256), R), dim3(256), 0, c.s, wk.V, wk.w,
+                         ld, vstride, md.offset, md.offset + md.hp.n, j + 1, mi * R, S, h);
+      LAUNCHCHECK();
+      ++mi;
+    }
+  }
+  norms_dev(c, wk.w, wk.npart, wk.nrm);
+  int mi = 0;
+  for (auto &md : c.pl->mesh) {
+    hipLaunchKernelGGL(k_normalize, dim3(nblk(md.hp.n, 256), R), dim3(256), 0, c.s, wk.w,
+                       wk.V + (j + 1) * vstride, ld, md.offset, md.offset + md.hp.n, mi * R,
+                       wk.nrm);
+    LAUNCHCHECK();
+    ++mi;
+  }
+  hipLaunchKernelGGL(k_givens, dim3(S), dim3(64), sizeof(double2) * (3 * (size_t)m + 1), c.s,
+                     wk.dev, wk.h1, wk.h2, wk.nrm, j, m, S);
+  LAUNCHCHECK();
+}
+
+// Steps j0 .. j1-1 as one HIP graph: captured on first use, replayed after.
+void run_segment_graph(Plan *pl, SolverState &st, Ctx &c, aim_precision prec, int j0, int j1) {
+  if (pl->work_gen != st.gen) {  // a grid work buffer moved since the capture
+    drop_graphs(st);
+    st.gen = pl->work_gen;
+  }
+  const auto key = std::make_tuple((int)prec, j0, j1);
+  auto it = st.graphs.find(key);
+  if (it == st.graphs.end()) {
+    HIPCHECK(hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal));
+    hipGraph_t g = nullptr;
+    try {
+      for (int j = j0; j < j1; ++j) arnoldi_step(c, prec, st.wk, j, st.m);
+    } catch (...) {
+      (void)hipStreamEndCapture(c.s, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIPCHECK(hipStreamEndCapture(c.s, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHECK(e);
+    it = st.graphs.emplace(key, ex).first;
+  }
+  HIPCHECK(hipGraphLaunch(it->second, c.s));
+}
+
 // Solve A d = rhs (d starts at 0) for every system to a relative residual
 // tol_s (estimated by the Arnoldi recurrence), restarted every m steps. The
 // Arnoldi step, the rotations and the residual estimate stay on the device;
 // the host reads the active flags every kCheckEvery iterations. Returns the
 // iterations used (lock-step count); `its` per system, `nprod` products.
-int gmres_run(Ctx &c, aim_precision prec, Work &wk, int m, const double2 *rhs, double2 *d,
-              const std::vector<double> &rhs_norm2, const std::vector<double> &tol_s, int max_iter,
-              std::vector<int> &its, int &nprod) {
+int gmres_run(Ctx &c, SolverState &st, aim_precision prec, bool graphs, const double2 *rhs,
+              double2 *d, const std::vector<double> &rhs_norm2, const std::vector<double> &tol_s,
+              int max_iter, std::vector<int> &its, int &nprod) {
+  Work &wk = st.wk;
+  const int m = st.m;
   const int S = c.S, R = c.R;
   const int64_t ld = c.ld, vstride = (int64_t)R * ld, cnt = vstride;
+  const int pi = prec == AIM_FP64 ? 0 : 1;
   HIPCHECK(hipMemsetAsync(d, 0, sizeof(double2) * cnt, c.s));
   std::vector<char> done(S, 0);
   for (int s = 0; s < S; ++s)
@@ -442,54 +595,26 @@ int gmres_run(Ctx &c, aim_precision prec, Work &wk, int m, const double2 *rhs, d
     HIPCHECK(hipMemcpyAsync(wk.dev.active, act.data(), sizeof(int) * S, hipMemcpyHostToDevice, c.s));
     HIPCHECK(hipMemcpyAsync(wk.dev.tol_abs, tabs.data(), sizeof(double) * S, hipMemcpyHostToDevice, c.s));
     HIPCHECK(hipMemcpyAsync(wk.dev.jend, zero.data(), sizeof(int) * S, hipMemcpyHostToDevice, c.s));
-    for (int j = 0; j < m && total < max_iter; ++j) {
-      // w = A D^-1 V[j]
-      hipLaunchKernelGGL(k_precond, dim3(nblk(ld, 256)), dim3(256), 0, c.s, wk.V + j * vstride, wk.z,
-                         c.dinv, ld, R);
-      LAUNCHCHECK();
-      apply(c, prec, wk.z, wk.w);
-      ++nprod;
-      ++total;
-      // two passes of classical Gram-Schmidt
-      for (int pass = 0; pass < 2; ++pass) {
-        double2 *h = pass == 0 ? wk.h1 : wk.h2;
-        int mi = 0;
-        for (auto &md : c.pl->mesh) {
-          const int64_t nb = dot_parts(md.hp.n) / kDotWaves;
-          hipLaunchKernelGGL(k_dots_part, dim3((unsigned)nb, R, nblk(j + 1, kGroup)),
-                             dim3(64 * kDotWaves), 0, c.s, wk.V, wk.w, ld, vstride, md.offset,
-                             md.offset + md.hp.n, j + 1, mi * R, S, wk.np_stride, wk.part);
-          LAUNCHCHECK();
-          hipLaunchKernelGGL(k_part_reduce, dim3(j + 1, R), dim3(64), 0, c.s, wk.part,
-                             wk.np_stride, (int)(nb * kDotWaves), mi * R, S, h);
-          LAUNCHCHECK();
-          hipLaunchKernelGGL(k_sub_basis, dim3(nblk(md.hp.n, 256), R), dim3(256), 0, c.s, wk.V,
-                             wk.w, ld, vstride, md.offset, md.offset + md.hp.n, j + 1, mi * R, S, h);
-          LAUNCHCHECK();
-          ++mi;
-        }
+    // segments of kCheckEvery steps between polls of the active flags; a full
+    // segment (or the cycle's last) is a graph once this precision has run
+    // directly on the current buffers (so no buffer is allocated in a capture)
+    for (int j = 0; j < m && total < max_iter;) {
+      const int j1 = std::min({j + kCheckEvery, m, j + (max_iter - total)});
+      const bool whole = (j1 - j == kCheckEvery) || j1 == m;
+      if (graphs && whole && st.warm[pi]) {
+        run_segment_graph(c.pl, st, c, prec, j, j1);
+      } else {
+        for (int jj = j; jj < j1; ++jj) arnoldi_step(c, prec, wk, jj, m);
+        st.warm[pi] = true;
       }
-      norms_dev(c, wk.w, wk.npart, wk.nrm);
-      {
-        int mi = 0;
-        for (auto &md : c.pl->mesh) {
-          hipLaunchKernelGGL(k_normalize, dim3(nblk(md.hp.n, 256), R), dim3(256), 0, c.s, wk.w,
-                             wk.V + (j + 1) * vstride, ld, md.offset, md.offset + md.hp.n, mi * R,
-                             wk.nrm);
-          LAUNCHCHECK();
-          ++mi;
-        }
-      }
-      hipLaunchKernelGGL(k_givens, dim3(S), dim3(64), sizeof(double2) * (3 * (size_t)m + 1), c.s,
-                         wk.dev, wk.h1, wk.h2, wk.nrm, j, m, S);
-      LAUNCHCHECK();
-      if ((j + 1) % kCheckEvery == 0 || j == m - 1) {
-        HIPCHECK(hipMemcpyAsync(act.data(), wk.dev.active, sizeof(int) * S, hipMemcpyDeviceToHost, c.s));
-        HIPCHECK(hipStreamSynchronize(c.s));
-        bool any = false;
-        for (int s = 0; s < S; ++s) any |= (bool)act[s];
-        if (!any) break;
-      }
+      nprod += j1 - j;
+      total += j1 - j;
+      j = j1;
+      HIPCHECK(hipMemcpyAsync(act.data(), wk.dev.active, sizeof(int) * S, hipMemcpyDeviceToHost, c.s));
+      HIPCHECK(hipStreamSynchronize(c.s));
+      bool any = false;
+      for (int s = 0; s < S; ++s) any |= (bool)act[s];
+      if (!any) break;
     }
     // d += D^-1 V y, y = H^-1 g per system (systems done before the cycle: jend = 0)
     hipLaunchKernelGGL(k_backsub, dim3(S), dim3(64), sizeof(double2) * (size_t)m, c.s, wk.dev,
@@ -515,13 +640,33 @@ int gmres_run(Ctx &c, aim_precision prec, Work &wk, int m, const double2 *rhs, d
 
 }  // namespace
 
+void solver_release(Plan *pl) {
+  if (!pl || !pl->solver) return;
+  SolverState &st = *pl->solver;
+  if (st.stream) (void)hipStreamSynchronize(st.stream);
+  drop_graphs(st);
+  for (void *p : st.bufs) dev_free(pl, p);
+  if (st.entry) (void)hipEventDestroy(st.entry);
+  if (st.stream) (void)hipStreamDestroy(st.stream);
+  delete pl->solver;
+  pl->solver = nullptr;
+}
+
 aim_status gmres_solve(Plan *pl, aim_precision prec, int R, const aim_planewave *waves,
-                       const aim_solve_opts &o, double2 *x, aim_solve_stats *st, hipStream_t s) {
+                       const aim_solve_opts &o, double2 *x, aim_solve_stats *st, hipStream_t caller) {
   auto t0 = std::chrono::steady_clock::now();
   const int S = pl->nmesh * R;
   const int m = o.restart;
   const int64_t ld = pl->n_total;
   const int64_t cnt = (int64_t)R * ld;
+  const bool graphs = !(o.flags & AIM_SOLVE_NO_GRAPH);
+  SolverState &ss = solver_state(pl, R, m);
+  // the solve runs on the solver's own stream (capturable), after the
+  // caller's stream has reached this call; it ends synchronised
+  const hipStream_t s = ss.stream;
+  HIPCHECK(hipEventRecord(ss.entry, caller));
+  HIPCHECK(hipStreamWaitEvent(s, ss.entry, 0));
+  Work &wk = ss.wk;
   std::vector<void *> tmp;
   auto alloc = [&](size_t bytes) {
     void *p = dev_alloc(pl, bytes);
@@ -530,36 +675,11 @@ aim_status gmres_solve(Plan *pl, aim_precision prec, int R, const aim_planewave 
   };
   aim_status result = AIM_OK;
   try {
-    Work wk;
-    wk.V = (double2 *)alloc(sizeof(double2) * (size_t)(m + 1) * cnt);
-    wk.z = (double2 *)alloc(sizeof(double2) * cnt);
-    wk.w = (double2 *)alloc(sizeof(double2) * cnt);
-    wk.h1 = (double2 *)alloc(sizeof(double2) * (size_t)(m + 1) * S);
-    wk.h2 = (double2 *)alloc(sizeof(double2) * (size_t)(m + 1) * S);
-    wk.y = (double2 *)alloc(sizeof(double2) * (size_t)(m + 1) * S);
-    wk.nrm = (double *)alloc(sizeof(double) * S);
-    for (auto &md : pl->mesh) wk.np_stride = std::max(wk.np_stride, dot_parts(md.hp.n));
-    wk.part = (double2 *)alloc(sizeof(double2) * (size_t)(m + 1) * S * wk.np_stride);
-    wk.npart = (double *)alloc(sizeof(double) * (size_t)S * kNormParts);
-    wk.dev.H = (double2 *)alloc(sizeof(double2) * (size_t)S * (m + 1) * m);
-    wk.dev.cs = (double2 *)alloc(sizeof(double2) * (size_t)S * m);
-    wk.dev.sn = (double2 *)alloc(sizeof(double2) * (size_t)S * m);
-    wk.dev.g = (double2 *)alloc(sizeof(double2) * (size_t)S * (m + 1));
-    wk.dev.active = (int *)alloc(sizeof(int) * S);
-    wk.dev.its = (int *)alloc(sizeof(int) * S);
-    wk.dev.jend = (int *)alloc(sizeof(int) * S);
-    wk.dev.tol_abs = (double *)alloc(sizeof(double) * S);
     double2 *b = (double2 *)alloc(sizeof(double2) * cnt);
     double2 *r = (double2 *)alloc(sizeof(double2) * cnt);
     double2 *dd = (double2 *)alloc(sizeof(double2) * cnt);
-    double2 *dinv = (double2 *)alloc(sizeof(double2) * ld);
-    for (auto &md : pl->mesh) {
-      hipLaunchKernelGGL(k_inv_diag, dim3(nblk(md.hp.n, 256)), dim3(256), 0, s, md.zdiag,
-                         dinv + md.offset, md.hp.n);
-      LAUNCHCHECK();
-      excitation_mesh(pl, md, R, waves, b + md.offset, ld, s);
-    }
-    Ctx c{pl, s, R, S, ld, dinv};
+    for (auto &md : pl->mesh) excitation_mesh(pl, md, R, waves, b + md.offset, ld, s);
+    Ctx c{pl, s, R, S, ld, ss.dinv};
     std::vector<double> b2, r2;
     norms(c, b, wk.npart, wk.nrm, b2);
     if (!o.warm_start) HIPCHECK(hipMemsetAsync(x, 0, sizeof(double2) * cnt, s));
@@ -583,7 +703,7 @@ aim_status gmres_solve(Plan *pl, aim_precision prec, int R, const aim_planewave 
       }
       std::vector<double> tol_s(S);
       for (int i = 0; i < S; ++i) tol_s[i] = r2[i] > 0 ? tol * std::sqrt(b2[i] / r2[i]) : 1.0;
-      total += gmres_run(c, AIM_FP64, wk, m, r, dd, r2, tol_s, o.max_iter, its, n64);
+      total += gmres_run(c, ss, AIM_FP64, graphs, r, dd, r2, tol_s, o.max_iter, its, n64);
       hipLaunchKernelGGL(k_axpy_real, dim3(nblk(cnt, 256)), dim3(256), 0, s, x, dd, cnt);
       LAUNCHCHECK();
       residual();
@@ -599,7 +719,8 @@ aim_status gmres_solve(Plan *pl, aim_precision prec, int R, const aim_planewave 
           double want = r2[i] > 0 ? 0.5 * tol * std::sqrt(b2[i] / r2[i]) : 1.0;
           tol_s[i] = std::max(want, 2e-6);
         }
-        total += gmres_run(c, AIM_MIXED, wk, m, r, dd, r2, tol_s, o.max_iter - total, its, n_low);
+        total += gmres_run(c, ss, AIM_MIXED, graphs, r, dd, r2, tol_s, o.max_iter - total, its,
+                           n_low);
         hipLaunchKernelGGL(k_axpy_real, dim3(nblk(cnt, 256)), dim3(256), 0, s, x, dd, cnt);
         LAUNCHCHECK();
         residual();
@@ -630,9 +751,11 @@ aim_status gmres_solve(Plan *pl, aim_precision prec, int R, const aim_planewave 
     }
     result = all_ok ? AIM_OK : AIM_ERR_NOCONV;
   } catch (...) {
+    (void)hipStreamSynchronize(s);
     for (void *p : tmp) dev_free(pl, p);
     throw;
   }
+  HIPCHECK(hipStreamSynchronize(s));
   for (void *p : tmp) dev_free(pl, p);
   return result;
 }

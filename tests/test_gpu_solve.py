@@ -196,3 +196,28 @@ def test_sphere_against_mie():
     _log(f"[sphere 1 lambda vs Mie] its={st[0]['iterations']} err_tt={err:.4f}")
     assert err < 0.1
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_graph_replays_match_direct_launches(prec):
+    """The Arnoldi segments captured into HIP graphs and replayed (later
+    restart cycles of the same solve, later solves) give bitwise the iterates
+    of direct launches; a product with more right-hand sides in between moves
+    the grid work buffers, and the solver captures again."""
+    from paper_1010_1456_amd import aim as A
+
+    s = setup("sphere05")
+    P = A.AIM_FP64 if prec == "fp64" else A.AIM_MIXED
+    waves = [(0.0, 0.0, 0), (0.7, 0.3, 1)]
+    kw = dict(tol=1e-9, restart=10, max_iter=40, raise_on_noconv=False)
+    x_direct, st_d = s.plan.solve(waves, P, graphs=False, **kw)
+    x_g1, st_1 = s.plan.solve(waves, P, **kw)  # captures on the first cycle, replays after
+    x_g2, st_2 = s.plan.solve(waves, P, **kw)  # replays only
+    big = torch.from_numpy(random_current(s.rwg.n, nrhs=5, seed=3)).cuda()
+    s.plan.matvec(big, A.AIM_FP64 if prec == "fp64" else A.AIM_MIXED_IO64)
+    torch.cuda.synchronize()
+    x_g3, st_3 = s.plan.solve(waves, P, **kw)  # buffers moved: captured again
+    assert st_d[0]["iterations"] > 10  # several restart cycles
+    for xg, stg in ((x_g1, st_1), (x_g2, st_2), (x_g3, st_3)):
+        assert torch.equal(xg, x_direct)
+        assert [q["iterations"] for q in stg] == [q["iterations"] for q in st_d]
