@@ -20,14 +20,23 @@ namespace {
 // its entries, so every node (also empty ones) is written exactly once, with
 // no atomics and no clearing pass, in a fixed order (bitwise reproducible).
 // Each 64-lane wave owns 64 consecutive nodes, whose entries are contiguous:
-// the wave loads them 64 at a time (coalesced), each lane forming one entry's
-// four products in LDS, and every lane then sums the slots of its own node.
+// the wave loads them epl * 64 at a time (coalesced; every lane has epl
+// independent gathers in flight), each lane forming its entries' four products
+// in LDS, and every lane then sums the slots of its own node. Entries per lane
+// per chunk (measured on the sphere: 2 for float, 1 for double; 4 is slower
+// for both)
+template <typename T>
+constexpr int anterp_epl() {
+  return sizeof(T) == 4 ? 2 : 1;
+}
 template <typename T, typename TX>
 __global__ void __launch_bounds__(256)
     k_anterp_gather(const cx<TX> *__restrict__ x, int64_t ldx, int nrhs,
                     const int32_t *__restrict__ node_ptr, const int32_t *__restrict__ ent_col,
                     const T *__restrict__ lamT, cx<T> *__restrict__ grid, int64_t V0) {
-  __shared__ cx<T> slot[4][64][4];  // [wave][entry][q]
+  constexpr int kEpl = anterp_epl<T>();
+  constexpr int C = 64 * kEpl;      // entries per chunk
+  __shared__ cx<T> slot[4][C][4];  // [wave][entry][q]
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t v0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + w) * 64;
   if (v0 >= V0) return;  // whole wave exits; no block-wide barrier is used
@@ -39,24 +48,33 @@ __global__ void __launch_bounds__(256)
   for (int r = 0; r < nrhs; ++r) {
     const cx<TX> *xr = x + (int64_t)r * ldx;
     T a[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-    for (int c0 = w0; c0 < w1; c0 += 64) {
-      const int e = c0 + lane;
-      if (e < w1) {
-        const cx<TX> xv = xr[ent_col[e]];
-        const T xa = (T)xv.x, xb = (T)xv.y;
+    for (int c0 = w0; c0 < w1; c0 += C) {
+      int col[kEpl];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const T wq = lamT[(int64_t)e * 4 + q];
-          cx<T> p;
-          p.x = wq * xa;
-          p.y = wq * xb;
-          slot[w][lane][q] = p;
+      for (int u = 0; u < kEpl; ++u) {
+        const int e = c0 + u * 64 + lane;
+        col[u] = e < w1 ? ent_col[e] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < kEpl; ++u) {
+        const int e = c0 + u * 64 + lane;
+        if (col[u] >= 0) {
+          const cx<TX> xv = xr[col[u]];
+          const T xa = (T)xv.x, xb = (T)xv.y;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const T wq = lamT[(int64_t)e * 4 + q];
+            cx<T> p;
+            p.x = wq * xa;
+            p.y = wq * xb;
+            slot[w][u * 64 + lane][q] = p;
+          }
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const int lo = (e0 > c0 ? e0 : c0) - c0, hi = (e1 < c0 + 64 ? e1 : c0 + 64) - c0;
+      const int lo = (e0 > c0 ? e0 : c0) - c0, hi = (e1 < c0 + C ? e1 : c0 + C) - c0;
       for (int k = lo; k < hi; ++k) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
