@@ -125,6 +125,8 @@ __device__ __forceinline__ V half_wave_sum(V v) {
 
 // y_m = j k eta [sum_{q<3} Lambda_mq . phi_q - k^-2 Lambda_md . phi_d]
 //       + sum_n Z^near_mn x_n. One 32-lane half-wave per row m.
+constexpr int kNearUnroll = 4;
+
 template <typename T, typename TX, typename TY>
 __global__ void __launch_bounds__(256)
     k_interp_near(const cx<T> *__restrict__ phi, int64_t V0, int nrhs, const T *__restrict__ lam,
@@ -155,12 +157,30 @@ __global__ void __launch_bounds__(256)
     nr.x = 0;
     nr.y = 0;
     const cx<TX> *xr = x + (int64_t)r * ldx;
-    for (int e = e0 + lane; e < e1; e += 32) {
-      const V z = nearv[e];
-      const cx<TX> xv = xr[cols[e]];
-      const T xa = (T)xv.x, xb = (T)xv.y;
-      nr.x += z.x * xa - z.y * xb;
-      nr.y += z.x * xb + z.y * xa;
+    // kNearUnroll entries per lane per pass, all gathers issued before any
+    // is used (rows hold ~80 entries: one pass of dependent loads, not three)
+    for (int eb = e0 + lane; eb < e1; eb += 32 * kNearUnroll) {
+      V z[kNearUnroll];
+      int c[kNearUnroll];
+#pragma unroll
+      for (int k = 0; k < kNearUnroll; ++k) {
+        const int e = eb + 32 * k;
+        const bool in = e < e1;
+        c[k] = in ? cols[e] : 0;
+        if (in) {
+          z[k] = nearv[e];
+        } else {
+          z[k].x = 0;
+          z[k].y = 0;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kNearUnroll; ++k) {
+        const cx<TX> xv = xr[c[k]];
+        const T xa = (T)xv.x, xb = (T)xv.y;
+        nr.x += z[k].x * xa - z[k].y * xb;
+        nr.y += z[k].x * xb + z[k].y * xa;
+      }
     }
     V acc;
     acc.x = -keta * far.y + nr.x;  // j k eta * far
