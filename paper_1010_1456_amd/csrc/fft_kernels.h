@@ -57,14 +57,20 @@ struct PlanC {
 
 constexpr int round_up_c(int a, int b) { return (a + b - 1) / b * b; }
 
-// Lines per work-group and threads per work-group of each pass shape.
+// Lines per work-group and threads per work-group of each pass shape: a
+// tile spans row_bytes of consecutive lines, fewer if the lines' butterflies
+// or their LDS exchange would not fit one work-group.
 template <typename T, class PC>
-constexpr int tile_strided() {
-  int B = sizeof(T) == 4 ? 16 : 8;  // 128-byte rows
+constexpr int tile_rows(int row_bytes) {
+  int B = row_bytes / (int)sizeof(cx<T>);
   while (B > 1 && (PC::maxnb() * B > 1024 ||
                    (PC::ns > 1 && (long)PC::P * B * (long)sizeof(cx<T>) > kLdsBudget)))
     B /= 2;
   return B;
+}
+template <typename T, class PC>
+constexpr int tile_strided() {
+  return tile_rows<T, PC>(128);  // 128-byte rows (64-byte rows measured slower)
 }
 template <typename T, class PC>
 constexpr int threads_strided() {
@@ -74,7 +80,7 @@ constexpr int threads_strided() {
 // slower on the 324-point plan)
 template <typename T, class PC>
 constexpr int tile_mid() {
-  return tile_strided<T, PC>();
+  return tile_rows<T, PC>(128);
 }
 template <typename T, class PC>
 constexpr int threads_mid() {
