@@ -22,7 +22,8 @@ namespace {
 // Each 64-lane wave owns 64 consecutive nodes, whose entries are contiguous:
 // the wave loads them epl * 64 at a time (coalesced; every lane has epl
 // independent gathers in flight), each lane forming its entries' four products
-// in LDS, and every lane then sums the slots of its own node. Entries per lane
+// in LDS, and every lane then sums the slots of its own node (one right-hand
+// side per blockIdx.y). Entries per lane
 // per chunk (measured on the sphere: 2 for float, 1 for double; 4 is slower
 // for both)
 template <typename T>
@@ -45,7 +46,8 @@ __global__ void __launch_bounds__(256)
   const int64_t vend = (v0 + 64 < V0) ? v0 + 64 : V0;
   const int e0 = ok ? node_ptr[v] : 0, e1 = ok ? node_ptr[v + 1] : 0;
   const int w0 = node_ptr[v0], w1 = node_ptr[vend];
-  for (int r = 0; r < nrhs; ++r) {
+  {
+    const int r = blockIdx.y;  // right-hand side
     const cx<TX> *xr = x + (int64_t)r * ldx;
     T a[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
     for (int c0 = w0; c0 < w1; c0 += C) {
@@ -140,7 +142,8 @@ __global__ void __launch_bounds__(256)
   if (m >= n) return;  // both rows of a wave exit together or each half runs alone
   const int64_t a = anchor_lin[m];
   const int e0 = rowptr[m], e1 = rowptr[m + 1];
-  for (int r = 0; r < nrhs; ++r) {
+  {
+    const int r = blockIdx.y;  // right-hand side
     V far;
     far.x = 0;
     far.y = 0;
@@ -284,12 +287,16 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
   const fftk::LineMap m2 = fftk::blocked_map(V2, Nx, Py, blk);
   mark(0);
   // projection fused with the forward z pass: the projected grid is never
-  // stored (except for inspection, or for FFT lengths without a fused kernel)
-  if (stop <= 1 || !md.fuse_proj[prec] ||
+  // stored (except for inspection, or for FFT lengths without a fused kernel).
+  // The variant is tuned on one right-hand side and walks the right-hand
+  // sides in turn, so several take the two-launch form (right-hand sides in
+  // parallel).
+  if (stop <= 1 || !md.fuse_proj[prec] || nrhs > 1 ||
       !anterp_fftz(x, ldx, nrhs, md.node_ptr, md.ent_col, lamT_of<T>(md), Nz, (int64_t)Nx * Ny, g1,
                    Pzs, (int64_t)Nx * Ny * Pzs, tw_of<T>(md, 2), md.plan[2], s)) {
-    hipLaunchKernelGGL((k_anterp_gather<T, TX>), dim3((unsigned)((V0 + 255) / 256)), dim3(256), 0,
-                       s, x, ldx, nrhs, md.node_ptr, md.ent_col, lamT_of<T>(md), g0, V0);
+    hipLaunchKernelGGL((k_anterp_gather<T, TX>), dim3((unsigned)((V0 + 255) / 256), nrhs),
+                       dim3(256), 0, s, x, ldx, nrhs, md.node_ptr, md.ent_col, lamT_of<T>(md), g0,
+                       V0);
     LAUNCHCHECK();
     mark(1);
     if (stop <= 1) return;
@@ -323,7 +330,7 @@ void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, 
   const int64_t V0 = (int64_t)h.grid[0] * h.grid[1] * h.grid[2];
   const int rows_per_block = 8;
   const int64_t blocks = (h.n + rows_per_block - 1) / rows_per_block;
-  hipLaunchKernelGGL((k_interp_near<T, TX, TY>), dim3((unsigned)blocks), dim3(32 * rows_per_block),
+  hipLaunchKernelGGL((k_interp_near<T, TX, TY>), dim3((unsigned)blocks, nrhs), dim3(32 * rows_per_block),
                      0, s, phi, V0, nrhs, lam_of<T>(md), md.anchor_lin, md.stencil_off, h.K,
                      md.rowptr, md.cols, near_of<T>(md), x, ldx, y, ldy, h.n,
                      (T)(h.k * kEta0), (T)(1.0 / (h.k * h.k)));
