@@ -91,6 +91,12 @@ using cx = typename vec2_of<T>::type;
 // 128 bytes of complex values
 template <typename T>
 constexpr int kGridBlock = 128 / (int)sizeof(cx<T>);
+// fewer padded kz than one such run (a flat scatterer): the grid between the
+// passes is kept kz-outer instead, [F][Pz][Nx][Ny] and [F][Pz][Nx][Py]
+template <typename T>
+constexpr bool thin_layout(int Pz) {
+  return Pz < kGridBlock<T>;
+}
 
 struct MeshDev {
   HostPlan hp;
@@ -164,12 +170,13 @@ void autotune_mesh(Plan *pl, MeshDev &md, hipStream_t s);
 
 namespace fftk {
 struct LineMap;
+struct ContigMap;
 }
 
 // FFT passes (fft_*.hip); one overload per precision, dispatching on pl.P
 #define AIM_DECLARE_FFT(V)                                                                       \
   void fft_pass_contig(const V *in, V *out, const FftPlan &pl, int n_in, int n_out,              \
-                       int64_t lines, int64_t in_line_stride, int64_t out_line_stride,           \
+                       int64_t lines, const fftk::ContigMap &imap, const fftk::ContigMap &omap,  \
                        bool inverse, const V *tw, hipStream_t s);                                \
   void fft_pass_strided(const V *in, V *out, const FftPlan &pl, int n_in, int n_out,             \
                         int64_t outer, int64_t inner, const fftk::LineMap &imap,                 \

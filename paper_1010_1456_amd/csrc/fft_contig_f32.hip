@@ -3,13 +3,13 @@
 
 namespace aim {
 void fft_pass_contig(const float2 *in, float2 *out, const FftPlan &pl, int n_in, int n_out,
-                     int64_t lines, int64_t in_ls, int64_t out_ls, bool inverse, const float2 *tw,
-                     hipStream_t s) {
+                     int64_t lines, const fftk::ContigMap &imap, const fftk::ContigMap &omap,
+                     bool inverse, const float2 *tw, hipStream_t s) {
   if (lines <= 0) return;
   switch (pl.P) {
 #define AIM_X(P, a, b, c)                                                                     \
   case P:                                                                                     \
-    fftk::launch_contig<float, fftk::PlanC<a, b, c>>(in, out, n_in, n_out, lines, in_ls, out_ls, \
+    fftk::launch_contig<float, fftk::PlanC<a, b, c>>(in, out, n_in, n_out, lines, imap, omap, \
                                                    inverse, tw, s);                           \
     return;
     AIM_FOR_EACH_FFT_PLAN(AIM_X)

@@ -102,7 +102,8 @@ constexpr int threads_contig() {
 template <typename T, bool INV, class PC>
 __global__ void __launch_bounds__((threads_contig<T, PC>()))
     k_fft_contig(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, int n_in, int n_out,
-                 int64_t lines, int64_t in_ls, int64_t out_ls, const cx<T> *__restrict__ tw, int B) {
+                 int64_t lines, ContigMap imap, ContigMap omap, const cx<T> *__restrict__ tw,
+                 int B) {
   using V = cx<T>;
   extern __shared__ unsigned char smem_raw[];
   V *lds = reinterpret_cast<V *>(smem_raw);
@@ -119,17 +120,17 @@ __global__ void __launch_bounds__((threads_contig<T, PC>()))
     constexpr bool first = (s == 0), last = (s == PC::ns - 1);
     const int b = threadIdx.x / nb, beta = threadIdx.x - b * nb;
     const bool active = (b < B) && (line0 + b < lines);
-    const V *gin = in + (line0 + b) * in_ls;
-    V *gout = out + (line0 + b) * out_ls;
+    const V *gin = in + contig_base(imap, line0 + b);
+    V *gout = out + contig_base(omap, line0 + b);
     V *ll = lds + b * LS;
     (void)tw;
     auto ld = [&](int i) AIM_AI -> V {
-      if constexpr (first) return (i < n_in) ? gin[i] : mk<V>((T)0, (T)0);
+      if constexpr (first) return (i < n_in) ? gin[i * imap.es] : mk<V>((T)0, (T)0);
       else return ll[i];
     };
     auto st = [&](int i, V v) AIM_AI {
       if constexpr (last) {
-        if (i < n_out) gout[i] = v;
+        if (i < n_out) gout[i * omap.es] = v;
       } else {
         ll[i] = v;
       }
@@ -194,17 +195,18 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
   });
 }
 
-// x pass over data in the kz-blocked layout [nfield][Pz/blk][n_x][Py][blk]:
-// lines (ky, kz). A work-group owns a tile of B consecutive kz (B | blk, so
-// the tile lies in one kz block) at one ky in one field and runs the forward
-// transform, spectrum multiply and inverse transform of its lines. The
-// fields of a tile, and the fields of its mirror tile Py - ky (the same
-// octant rows), get consecutive numbers, and consecutive numbers go to the
-// same XCD (work-groups are dealt round-robin to the 8 XCDs), so the octant
-// rows a tile reads are mostly found in that XCD's L2. Global accesses are buffer
-// loads and stores: a work-group-uniform resource and scalar offset plus a
-// per-thread 32-bit offset fixed for the whole kernel (the launcher checks
-// the ranges), which keeps address arithmetic off the vector ALU.
+// x pass: forward transform along x, spectrum multiply and inverse transform
+// of every line (ky, kz) of every field. A work-group owns a tile of B lines
+// that are adjacent in memory (one 128-byte row: consecutive kz of the
+// kz-blocked layout, or consecutive ky of the thin layout) in one field. The
+// fields of a tile, and the fields of its mirror tile (Py - ky, resp.
+// Pz - kz: the same octant rows), get consecutive numbers, and consecutive
+// numbers go to the same XCD (work-groups are dealt round-robin to the 8
+// XCDs), so the octant rows a tile reads are mostly found in that XCD's L2.
+// Global accesses are buffer loads and stores: a work-group-uniform resource
+// and scalar offset plus a per-thread 32-bit offset fixed for the whole kernel
+// (the launcher checks the ranges), which keeps address arithmetic off the
+// vector ALU.
 constexpr int kXcd = 8;
 constexpr int kBufferWord3 = 0x00020000;  // raw buffer resource, 32-bit data format
 
@@ -250,7 +252,7 @@ struct MidLds {
   static constexpr int total = data + flat + mid_rows + last_rows;
 };
 
-template <typename T, class PC>
+template <typename T, class PC, bool KYL>
 __global__ void __launch_bounds__((threads_mid<T, PC>()), (mid_min_waves<T>()))
     k_fft_mid(cx<T> *__restrict__ data, int n_x, int nfield, int Py, int Pz, int ntile, int slots,
               int Hy, int Hz, const cx<T> *__restrict__ ghat, const cx<T> *__restrict__ tw, int blk,
@@ -272,31 +274,37 @@ __global__ void __launch_bounds__((threads_mid<T, PC>()), (mid_min_waves<T>()))
   constexpr int NIN0 = HALF ? R0 / 2 : R0;        // first-stage inputs per butterfly
   constexpr int RM = PC::r(ns - 1), LM = P / RM;  // middle stage (M' = 1)
 
-  // work number t = nfield (2 (fky ntile + kzt) + m) + field, ky = fky (m = 0)
-  // or Py - fky (m = 1)
+  // Lines run along x at (ky, kz). kz-blocked layout (KYL false): a tile is
+  // B consecutive kz (the tile axis) at one ky (the fixed axis). Thin layout
+  // [nfield][Pz][n_x][Py] (KYL true): B consecutive ky at one kz. Work number
+  // t = nfield (2 (ff ntile + kt) + m) + field: fixed index ff (m = 0) or its
+  // mirror Pf - ff (m = 1), which reads the same octant rows, tile kt.
+  const int Pt = KYL ? Py : Pz, Pf = KYL ? Pz : Py;
   const int t = (int)(blockIdx.x % kXcd) * slots + (int)(blockIdx.x / kXcd);
   const int field = t % nfield, tt = t / nfield;
   const int m = tt & 1, rest = tt >> 1;
-  const int fky = rest / ntile;
-  const int kzt = rest - fky * ntile;
-  if (2 * fky > Py) return;                      // padding: exit before any barrier
-  if (m && (fky == 0 || 2 * fky == Py)) return;  // row is its own mirror: m = 0 covers it
-  const int ky = m ? Py - fky : fky;
-  const int kz0 = kzt * B;
+  const int ff = rest / ntile;
+  const int kt = rest - ff * ntile;
+  if (2 * ff > Pf) return;                      // padding: exit before any barrier
+  if (m && (ff == 0 || 2 * ff == Pf)) return;  // its own mirror: m = 0 covers it
+  const int fixed = m ? Pf - ff : ff;
+  const int k0 = kt * B;
   const int b = threadIdx.x % B;
   const int beta = threadIdx.x / B;
-  const int kz = kz0 + b;
-  const bool line_ok = kz < Pz;
-  const int fkz = (kz <= Pz - kz) ? kz : Pz - kz;
+  const int kl = k0 + b;  // tile-axis index of this thread's line
+  const bool line_ok = kl < Pt;
+  const int fl = (kl <= Pt - kl) ? kl : Pt - kl;
+  const int fky = KYL ? fl : ff, fkz = KYL ? ff : fl;
   const int gplane = Hy * Hz;
-  const int es = Py * blk;  // elements between x and x + 1 of a line
-  // field data: resource over the tile's kz block of this field; the tile's
-  // first line starts at byte t0 of it, thread (b, beta) adds o_beta
+  const int es = KYL ? Py : Py * blk;  // elements between x and x + 1 of a line
+  // field data: resource over one kz block (one kz plane for KYL) of this
+  // field; the tile's first line starts at byte t0 of it, thread (b, beta)
+  // adds o_beta
   const int64_t blk_elems = (int64_t)n_x * es;
   const __amdgpu_buffer_rsrc_t fr =
-      buffer_of(data + field * fstride + (int64_t)(kz0 / blk) * blk_elems,
+      buffer_of(data + field * fstride + (int64_t)(KYL ? fixed : k0 / blk) * blk_elems,
                 (uint32_t)blk_elems * SV);
-  const uint32_t t0 = (uint32_t)(ky * blk + kz0 % blk) * SV;
+  const uint32_t t0 = (uint32_t)(KYL ? k0 : fixed * blk + k0 % blk) * SV;
   const uint32_t o_beta = (uint32_t)(b + beta * es) * SV;
 
   // spectrum values of the middle butterfly j = beta (kx = j + LM p): kx <
@@ -448,18 +456,19 @@ __global__ void __launch_bounds__((threads_mid<T, PC>()), (mid_min_waves<T>()))
 }
 
 template <typename T, class PC>
-void launch_contig(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t lines, int64_t in_ls,
-                   int64_t out_ls, bool inverse, const cx<T> *tw, hipStream_t s) {
+void launch_contig(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t lines,
+                   const ContigMap &imap, const ContigMap &omap, bool inverse, const cx<T> *tw,
+                   hipStream_t s) {
   constexpr int B = tile_contig<T, PC>();
   constexpr int threads = threads_contig<T, PC>();
   const size_t lds = PC::ns > 1 ? ((size_t)B * (PC::P + 1) + PC::P) * sizeof(cx<T>) : 0;
   const int64_t blocks = (lines + B - 1) / B;
   if (inverse)
     hipLaunchKernelGGL((k_fft_contig<T, true, PC>), dim3((unsigned)blocks), dim3(threads), lds, s,
-                       in, out, n_in, n_out, lines, in_ls, out_ls, tw, B);
+                       in, out, n_in, n_out, lines, imap, omap, tw, B);
   else
     hipLaunchKernelGGL((k_fft_contig<T, false, PC>), dim3((unsigned)blocks), dim3(threads), lds, s,
-                       in, out, n_in, n_out, lines, in_ls, out_ls, tw, B);
+                       in, out, n_in, n_out, lines, imap, omap, tw, B);
   LAUNCHCHECK();
 }
 
@@ -481,27 +490,39 @@ void launch_strided(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t ou
   LAUNCHCHECK();
 }
 
+// blk > 0: kz-blocked layout [nfield][ceil(Pz/blk)][n_x][Py][blk], tiles of
+// consecutive kz; blk == 0: thin layout [nfield][Pz][n_x][Py] (few kz, as
+// for a flat scatterer), tiles of consecutive ky
 template <typename T, class PC>
 void launch_mid(cx<T> *data, int n_x, int nfield, int Py, int Pz, int Hy, int Hz,
                 const cx<T> *ghat, const cx<T> *tw, int blk, int64_t fstride, hipStream_t s) {
   constexpr int B = tile_mid<T, PC>();
   constexpr int threads = threads_mid<T, PC>();
+  const bool kyl = blk == 0;
   if (PC::r(0) % 2 == 0 && 2 * n_x > PC::P)  // the half-pruned first/last stages need it
     throw Error(AIM_ERR_ARG, "x pass: more than P/2 sources on a line");
-  if (blk <= 0 || blk % B != 0) throw Error(AIM_ERR_ARG, "x pass: tile does not divide the kz block");
-  // 32-bit buffer offsets: one kz block of a field, and the octant
-  if ((uint64_t)n_x * Py * blk * sizeof(cx<T>) >= (1ull << 31) ||
+  if (blk < 0 || (!kyl && blk % B != 0))
+    throw Error(AIM_ERR_ARG, "x pass: tile does not divide the kz block");
+  // 32-bit buffer offsets: one kz block (kz plane) of a field, and the octant
+  if ((uint64_t)n_x * Py * (kyl ? 1 : blk) * sizeof(cx<T>) >= (1ull << 31) ||
       (uint64_t)Hy * Hz * (PC::P / 2 + 1) * sizeof(cx<T>) >= (1ull << 31))
     throw Error(AIM_ERR_ARG, "x pass: grid too large for 32-bit offsets");
-  const int ntile = (Pz + B - 1) / B;
+  const int Pt = kyl ? Py : Pz, Pf = kyl ? Pz : Py;  // tile axis, fixed axis
+  const int ntile = (Pt + B - 1) / B;
   const size_t lds = (size_t)MidLds<T, PC>::total * sizeof(cx<T>);
-  // work items (fky, kz tile, mirror, field), fky = 0 .. Py/2, dealt to the
-  // XCDs in 8 contiguous ranges
-  const int64_t items = 2 * ((int64_t)Py / 2 + 1) * ntile * nfield;
+  // work items (folded fixed index 0 .. Pf/2, tile, mirror, field), dealt to
+  // the XCDs in 8 contiguous ranges
+  const int64_t items = 2 * ((int64_t)Pf / 2 + 1) * ntile * nfield;
   const int64_t slots = (items + kXcd - 1) / kXcd;
   if (slots * kXcd > INT32_MAX) throw Error(AIM_ERR_ARG, "x pass: too many tiles");
-  hipLaunchKernelGGL((k_fft_mid<T, PC>), dim3((unsigned)(slots * kXcd)), dim3(threads), lds, s,
-                     data, n_x, nfield, Py, Pz, ntile, (int)slots, Hy, Hz, ghat, tw, blk, fstride);
+  if (kyl)
+    hipLaunchKernelGGL((k_fft_mid<T, PC, true>), dim3((unsigned)(slots * kXcd)), dim3(threads),
+                       lds, s, data, n_x, nfield, Py, Pz, ntile, (int)slots, Hy, Hz, ghat, tw, blk,
+                       fstride);
+  else
+    hipLaunchKernelGGL((k_fft_mid<T, PC, false>), dim3((unsigned)(slots * kXcd)), dim3(threads),
+                       lds, s, data, n_x, nfield, Py, Pz, ntile, (int)slots, Hy, Hz, ghat, tw, blk,
+                       fstride);
   LAUNCHCHECK();
 }
 

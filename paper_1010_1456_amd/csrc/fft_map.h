@@ -52,5 +52,22 @@ inline LineMap blocked_map(int64_t field_stride, int Nx, int Py, int blk) {
   return m;
 }
 
+// Line addressing of the contiguous passes: line L = f per + l starts at
+// f fs + l ls (per = 0: no split, L ls), its elements es apart.
+struct ContigMap {
+  int64_t per, fs, ls, es;
+};
+__host__ __device__ inline int64_t contig_base(const ContigMap &m, int64_t L) {
+  if (m.per == 0) return L * m.ls;
+  const int64_t f = L / m.per;
+  return f * m.fs + (L - f * m.per) * m.ls;
+}
+// lines ls apart, elements adjacent
+inline ContigMap contig_map(int64_t ls) { return ContigMap{0, 0, ls, 1}; }
+// per lines of each of the fields fs apart, lines ls apart, elements es apart
+inline ContigMap contig_map(int64_t per, int64_t fs, int64_t ls, int64_t es) {
+  return ContigMap{per, fs, ls, es};
+}
+
 }  // namespace fftk
 }  // namespace aim

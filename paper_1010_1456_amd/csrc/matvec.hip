@@ -101,6 +101,17 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// thin [F][Pz][A] grid -> plain [F][A][Pz] (inspection)
+template <typename T>
+__global__ void k_kz_inner(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, int64_t F,
+                           int64_t A, int Pz) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= F * A * Pz) return;
+  const int kz = (int)(t % Pz);
+  const int64_t a = (t / Pz) % A, f = t / (Pz * A);
+  out[t] = in[(f * Pz + kz) * A + a];
+}
+
 // kz-blocked [F][Pz/blk][Nx][Py][blk] grid -> plain [F][Nx][Py][Pz] (inspection)
 template <typename T>
 __global__ void k_unblock(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, int64_t F, int Nx,
@@ -277,6 +288,42 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
   const int64_t F = 4 * (int64_t)nrhs;
   const int64_t V0 = (int64_t)Nx * Ny * Nz;
   const int blk = kGridBlock<T>;
+  if (thin_layout<T>(Pz)) {
+    // few kz (a flat scatterer): kz-outer layouts g1 [F][Pz][Nx][Ny] and
+    // g2 [F][Pz][Nx][Py], no row padding; the y lines are contiguous, the x
+    // pass tiles consecutive ky
+    const int64_t A1 = (int64_t)Nx * Ny, V1 = Pz * A1, V2 = (int64_t)Pz * Nx * Py;
+    cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * V0);
+    cx<T> *g1 = (cx<T> *)work_buffer(pl, prec, 1, sizeof(cx<T>) * F * V1);
+    cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2);
+    mark(0);
+    hipLaunchKernelGGL((k_anterp_gather<T, TX>), dim3((unsigned)((V0 + 255) / 256), nrhs),
+                       dim3(256), 0, s, x, ldx, nrhs, md.node_ptr, md.ent_col, lamT_of<T>(md), g0,
+                       V0);
+    LAUNCHCHECK();
+    mark(1);
+    if (stop <= 1) return;
+    fft_pass_contig(g0, g1, md.plan[2], Nz, Pz, F * A1, fftk::contig_map(Nz),
+                    fftk::contig_map(A1, V1, 1, A1), false, tw_of<T>(md, 2), s);
+    mark(2);
+    if (stop <= 2) return;
+    fft_pass_contig(g1, g2, md.plan[1], Ny, Py, F * Pz * Nx, fftk::contig_map(Ny),
+                    fftk::contig_map(Py), false, tw_of<T>(md, 1), s);
+    mark(3);
+    if (stop <= 3) return;
+    fft_mid_pass(g2, md.plan[0], Nx, (int)F, Py, Pz, md.H[0], md.H[1], md.H[2], ghat_of<T>(md),
+                 tw_of<T>(md, 0), 0, V2, s);
+    mark(4);
+    if (stop <= 4) return;
+    fft_pass_contig(g2, g1, md.plan[1], Py, Ny, F * Pz * Nx, fftk::contig_map(Py),
+                    fftk::contig_map(Ny), true, tw_of<T>(md, 1), s);
+    mark(5);
+    if (stop <= 5) return;
+    fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * A1, fftk::contig_map(A1, V1, 1, A1),
+                    fftk::contig_map(Nz), true, tw_of<T>(md, 2), s);
+    mark(6);
+    return;
+  }
   const int Pzs = (Pz + blk - 1) / blk * blk;  // z rows padded to 128-byte multiples
   const int64_t V1 = (int64_t)Nx * Ny * Pzs;
   const int64_t V2 = (int64_t)Nx * Py * ((Pz + blk - 1) / blk * blk);  // kz-blocked
@@ -300,7 +347,8 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     LAUNCHCHECK();
     mark(1);
     if (stop <= 1) return;
-    fft_pass_contig(g0, g1, md.plan[2], Nz, Pz, F * Nx * Ny, Nz, Pzs, false, tw_of<T>(md, 2), s);
+    fft_pass_contig(g0, g1, md.plan[2], Nz, Pz, F * Nx * Ny, fftk::contig_map(Nz),
+                    fftk::contig_map(Pzs), false, tw_of<T>(md, 2), s);
   } else {
     mark(1);
   }
@@ -316,7 +364,8 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
   fft_pass_strided(g2, g1, md.plan[1], Py, Ny, F * Nx, Pz, m2, m1, true, tw_of<T>(md, 1), s);
   mark(5);
   if (stop <= 5) return;
-  fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * Nx * Ny, Pzs, Nz, true, tw_of<T>(md, 2), s);
+  fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * Nx * Ny, fftk::contig_map(Pzs),
+                  fftk::contig_map(Nz), true, tw_of<T>(md, 2), s);
   mark(6);
 }
 
@@ -347,6 +396,15 @@ void copy_far_stage(Plan *pl, MeshDev &md, int nrhs, int stage, void *out, hipSt
   const int64_t F = 4 * (int64_t)nrhs;
   const int blk = kGridBlock<T>;
   const int64_t V2 = (int64_t)Nx * Py * ((Pz + blk - 1) / blk * blk);
+  if (thin_layout<T>(Pz) && stage >= 2 && stage <= 5) {  // [F][Pz][A] -> [F][A][Pz]
+    const int64_t A = (stage == 3 || stage == 4) ? (int64_t)Nx * Py : (int64_t)Nx * Ny;
+    const int64_t tot = F * A * Pz;
+    hipLaunchKernelGGL((k_kz_inner<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                       (const cx<T> *)pl->work[prec][(stage == 3 || stage == 4) ? 2 : 1],
+                       (cx<T> *)out, F, A, Pz);
+    LAUNCHCHECK();
+    return;
+  }
   if (stage == 3 || stage == 4) {
     const int64_t tot = F * Nx * Py * Pz;
     hipLaunchKernelGGL((k_unblock<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
@@ -377,7 +435,8 @@ void autotune_mesh(Plan *pl, MeshDev &md, hipStream_t s) {
     HIPCHECK(hipMemsetAsync(x, 0, sizeof(double2) * n, s));
     for (int prec = 0; prec < 2; ++prec) {
       if (prec == 1 && !pl->mixed) break;
-      if (!fft_anterp_fused(md.plan[2])) {
+      const bool thin = prec == 0 ? thin_layout<double>(md.hp.pad[2]) : thin_layout<float>(md.hp.pad[2]);
+      if (thin || !fft_anterp_fused(md.plan[2])) {
         md.fuse_proj[prec] = 0;
         continue;
       }

@@ -373,7 +373,8 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
     hipLaunchKernelGGL(k_embed_green, dim3(blocks_for(tot, 256)), dim3(256), 0, s, e0, Px, Py, Pz,
                        h.grid[0], h.grid[1], h.grid[2], h.k, h.h);
     LAUNCHCHECK();
-    fft_pass_contig(e0, e1, md.plan[2], Pz, Pz, (int64_t)Px * Py, Pz, Pz, false, md.tw64[2], s);
+    fft_pass_contig(e0, e1, md.plan[2], Pz, Pz, (int64_t)Px * Py, fftk::contig_map(Pz),
+                    fftk::contig_map(Pz), false, md.tw64[2], s);
     const fftk::LineMap my = fftk::plain_map((int64_t)Py * Pz, Pz);
     const fftk::LineMap mx = fftk::plain_map(0, (int64_t)Py * Pz);
     fft_pass_strided(e1, e0, md.plan[1], Py, Py, Px, Pz, my, my, false, md.tw64[1], s);
