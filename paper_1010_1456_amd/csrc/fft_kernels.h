@@ -239,16 +239,20 @@ template <typename T>
 constexpr int mid_min_waves() {
   return sizeof(T) == 4 ? 4 : 3;
 }
-// LDS of the x pass: the tile's lines, the twiddle table (3-stage plans), and
-// the row tables of the middle stage and of the inverse's last stage
+// LDS of the x pass: the tile's lines, and for two-stage plans the row tables
+// of the middle stage and of the inverse's last stage (about P entries), for
+// three-stage plans the twiddle table of exp(-2 pi i e / P): row tables of
+// long lines would cost about as much LDS as the lines themselves (measured on
+// the 2592-point plan: 1.66 ms with row tables, 1.17 ms without)
 template <typename T, class PC>
 struct MidLds {
   static constexpr int P = PC::P, ns = PC::ns, R0 = PC::r(0), RM = PC::r(ns - 1);
+  static constexpr bool rows = ns == 2;
   static constexpr int data = ns > 1 ? P * tile_mid<T, PC>() : 0;
   static constexpr int flat = ns > 2 ? P : 0;
-  static constexpr int mid_rows = ns > 1 ? (P / RM) * (RM - 1) : 0;
+  static constexpr int mid_rows = rows ? (P / RM) * (RM - 1) : 0;
   static constexpr bool same_rows = (R0 == RM);  // square two-stage plans share one table
-  static constexpr int last_rows = (ns > 1 && !same_rows) ? (P / R0) * (R0 - 1) : 0;
+  static constexpr int last_rows = (rows && !same_rows) ? (P / R0) * (R0 - 1) : 0;
   static constexpr int total = data + flat + mid_rows + last_rows;
 };
 
@@ -348,7 +352,7 @@ __global__ void __launch_bounds__((threads_mid<T, PC>()), (mid_min_waves<T>()))
   V *twr = ML::same_rows ? twm : twm + ML::mid_rows;  // inverse last stage rows
   if constexpr (ML::flat > 0)
     for (int i = threadIdx.x; i < P; i += blockDim.x) twl[i] = tw[i];
-  if constexpr (ns > 1) {
+  if constexpr (ML::rows) {
     for (int i = threadIdx.x; i < ML::mid_rows; i += blockDim.x) {
       const int jj = i / (RM - 1), q = i - jj * (RM - 1) + 1;
       twm[i] = tw[jj * q];
@@ -409,11 +413,18 @@ __global__ void __launch_bounds__((threads_mid<T, PC>()), (mid_min_waves<T>()))
         });
       __syncthreads();
       if (act_mid) {
-        const V *row = twm + j * (RM - 1);
-        static_for<RM - 1>([&](auto q_) AIM_AI {
-          constexpr int q = decltype(q_)::value + 1;
-          v[q] = tw_mul<false>(v[q], row, q - 1);
-        });
+        if constexpr (ML::rows) {
+          const V *row = twm + j * (RM - 1);
+          static_for<RM - 1>([&](auto q_) AIM_AI {
+            constexpr int q = decltype(q_)::value + 1;
+            v[q] = tw_mul<false>(v[q], row, q - 1);
+          });
+        } else {
+          static_for<RM - 1>([&](auto q_) AIM_AI {
+            constexpr int q = decltype(q_)::value + 1;
+            v[q] = tw_mul<false>(v[q], twl, j * q);
+          });
+        }
         Dft<RM, false, V>::run(v);
         V g[RM];
         spectrum(g);
@@ -448,8 +459,8 @@ __global__ void __launch_bounds__((threads_mid<T, PC>()), (mid_min_waves<T>()))
       if (active) stage_load<R, true, V>(v, beta, Mp, ld);
       if constexpr (!last) __syncthreads();
       if (active)
-        stage_compute_store_p<R, true, false, (last && HALF) ? R / 2 : R, last>(
-            v, beta, L, Mp, last ? twr : twl, st);
+        stage_compute_store_p<R, true, false, (last && HALF) ? R / 2 : R, last && ML::rows>(
+            v, beta, L, Mp, (last && ML::rows) ? twr : twl, st);
       if constexpr (!last) __syncthreads();
     });
   }

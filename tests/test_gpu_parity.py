@@ -164,3 +164,65 @@ def test_matvec_direct_sum_agrees():
     ref = oaim.matvec_direct(c.op, x)
     y = c.plan.matvec(torch.from_numpy(x).cuda(), A.AIM_FP64).cpu().numpy()
     assert rel(y, ref) <= 1e-10
+
+
+def _strip_mesh(length_lambda, width_lambda, freq_hz, per_lambda=9):
+    """Structured rectangular plate in z = 0 (squares split along the
+    (i, j)-(i+1, j+1) diagonal, counter-clockwise about +z)."""
+    from workloads.meshes import wavelength
+
+    lam = wavelength(freq_hz)
+    nx, ny = round(length_lambda * per_lambda), round(width_lambda * per_lambda)
+    xs = (np.arange(nx + 1) / per_lambda - length_lambda / 2) * lam
+    ys = (np.arange(ny + 1) / per_lambda - width_lambda / 2) * lam
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    verts = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], axis=1)
+    vid = lambda i, j: i * (ny + 1) + j  # noqa: E731
+    tris = []
+    for i in range(nx):
+        for j in range(ny):
+            a, b, c, d = vid(i, j), vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1)
+            tris += [(a, b, c), (a, c, d)]
+    return verts, np.asarray(tris, dtype=np.int32)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_far_stages_long_x_lines(prec):
+    """A 40 x 0.5 lambda strip: a three-stage x FFT (864 points) with few lines
+    per x-pass work-group (4 for c64, 2 for c128) in the thin layout. Every
+    pass against numpy FFTs of the oracle's projected grid."""
+    from paper_1010_1456_amd import aim as A
+
+    freq = 0.3e9
+    verts, tris = _strip_mesh(40.0, 0.5, freq)
+    k = wavenumber(freq)
+    lam_m = 299_792_458.0 / freq
+    rwg = build_rwg(verts, tris)
+    grid = oaim.grid_plan(rwg.verts, 0.1 * lam_m, 2)
+    anc = oaim.anchors(grid, rwg.centre)
+    op = oaim.AIMOperator(rwg=rwg, k=k, grid=grid, anc=anc, lam=oaim.projection(rwg, grid, anc),
+                          near=None, zmom_diag=None)
+    plan = A.Plan([(verts, tris, freq)])
+    Px, Py, Pz = plan.info()["pad"][0]
+    assert Px >= 769  # at most 4 (c64) / 2 (c128) lines per x-pass work-group
+    ghat = oaim.green_spectrum(k, grid, (Px, Py, Pz))
+    P = A.AIM_FP64 if prec == "fp64" else A.AIM_MIXED
+    tol = 1e-12 if prec == "fp64" else 3e-6
+    x = random_current(rwg.n, nrhs=2, seed=11)
+    Nx, Ny, Nz = (int(v) for v in grid.n)
+    s = oaim.anterpolate(op, x).reshape(2, 4, Nx, Ny, Nz)
+    st2 = np.fft.fft(s, n=Pz, axis=4)
+    st3 = np.fft.fft(st2, n=Py, axis=3)
+    full = np.fft.fft(st3, n=Px, axis=2) * (ghat / (Px * Py * Pz))[None, None]
+    st4 = (np.fft.ifft(full, axis=2) * Px)[:, :, :Nx]
+    st5 = (np.fft.ifft(st4, axis=3) * Py)[:, :, :, :Ny]
+    st6 = (np.fft.ifft(st5, axis=4) * Pz)[..., :Nz]
+    refs = {1: s, 2: st2, 3: st3, 4: st4, 5: st5, 6: st6}
+    xt = torch.from_numpy(x).cuda()
+    for stage in range(1, 7):
+        _log(f"[far_stages strip {prec}] stage {stage}")
+        got = plan.far_stage(0, xt, stage, P).cpu().numpy()
+        r = refs[stage]
+        err = np.abs(got - r).max() / np.abs(r).max()
+        assert err <= tol, (stage, err)
+    plan.close()
