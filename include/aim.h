@@ -136,6 +136,10 @@ typedef struct {
   int32_t fused_projection[AIM_MAX_MESH][2]; /* [mesh][0 FP64, 1 mixed]: 1 if the projection
                                                runs inside the forward z pass (chosen by
                                                timing at set-up) */
+  int32_t planar_z[AIM_MAX_MESH];       /* z index of the one grid plane that holds every
+                                           projection weight (a flat scatterer lying in a
+                                           grid plane), else -1; the propagation then runs
+                                           on that plane alone with the 2-D spectrum */
   double device_bytes;                  /* device memory held by the plan */
 } aim_info;
 

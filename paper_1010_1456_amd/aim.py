@@ -78,7 +78,8 @@ class AimInfo(ctypes.Structure):
                 ("nnz", c_int64 * M), ("grid", (c_int32 * 3) * M), ("pad", (c_int32 * 3) * M),
                 ("h", c_double * M), ("x0", (c_double * 3) * M), ("k", c_double * M),
                 ("bytes_fp64", c_double * M), ("bytes_mixed", c_double * M),
-                ("fused_projection", (c_int32 * 2) * M), ("device_bytes", c_double)]
+                ("fused_projection", (c_int32 * 2) * M), ("planar_z", c_int32 * M),
+                ("device_bytes", c_double)]
 
 
 class AimSolveOpts(ctypes.Structure):
@@ -271,6 +272,7 @@ class Plan:
             bytes_mixed=[inf.bytes_mixed[i] for i in range(nm)],
             fused_projection=[(bool(inf.fused_projection[i][0]), bool(inf.fused_projection[i][1]))
                               for i in range(nm)],
+            planar_z=[inf.planar_z[i] for i in range(nm)],
             device_bytes=inf.device_bytes)
 
     def _stream(self, stream):

@@ -134,6 +134,13 @@ struct MeshDev {
   // tuned variants, per precision [0 = FP64, 1 = FP32]: projection fused with
   // the forward z pass (1) or two launches (0)
   int fuse_proj[2] = {0, 0};
+  // z index of the one grid plane holding every projection weight, or -1.
+  // Then the sources, and the fields the interpolation weighs, live on that
+  // plane only, and the propagation is the 2-D convolution on it with the
+  // spectrum of g(x, y, 0): the 3-D spectrum summed over kz (octant H0 x H1)
+  int planar_z = -1;
+  double2 *ghat2d64 = nullptr;
+  float2 *ghat2d32 = nullptr;
 };
 
 struct Plan;
@@ -202,10 +209,11 @@ AIM_DECLARE_ANTERP(double2, double, double2)
 
 // matvec (matvec.hip)
 // `ev` (optional) receives an event record before the first kernel and after
-// each stage: ev[0] .. ev[AIM_NSTAGE].
+// each stage: ev[0] .. ev[AIM_NSTAGE]. `full3d` (inspection): the 3-D passes
+// also for a scatterer in one grid plane.
 template <typename T, typename TX>
 void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, int stop_stage,
-                hipStream_t s, hipEvent_t *ev = nullptr);
+                hipStream_t s, hipEvent_t *ev = nullptr, bool full3d = false);
 template <typename T, typename TX, typename TY>
 void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, cx<TY> *y,
                  int64_t ldy, hipStream_t s, hipEvent_t *ev = nullptr);

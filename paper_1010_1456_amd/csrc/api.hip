@@ -90,6 +90,11 @@ static double model_bytes(const MeshDev &md, int sc, int sr) {
   const double V0 = Nx * Ny * Nz, V1 = Nx * Ny * Pz, V2 = Nx * Py * Pz;
   // per field: [projection write V0; z read V0] + z write V1; y: V1 + V2; x: 2 V2;
   // inverse y: V2 + V1; inverse z: V1 + V0; interpolation read V0
+  if (md.planar_z >= 0) {  // per field: projection V0, y passes 2 (Nx Ny + Nx Py), x 2 Nx Py,
+                           // interpolation V0; the 2-D spectrum
+    const double grid = 4.0 * sc * (2.0 * V0 + 2.0 * Nx * Ny + 4.0 * Nx * Py);
+    return vec + lam + nearb + (double)md.H[0] * md.H[1] * sc + grid;
+  }
   const double v0_terms = md.fuse_proj[sc == 16 ? 0 : 1] ? 2.0 : 4.0;
   const double grid = 4.0 * sc * (v0_terms * V0 + 4.0 * V1 + 4.0 * V2);
   return vec + lam + nearb + ghat + grid;
@@ -208,6 +213,7 @@ aim_status aim_plan_info(const aim_plan *plan, aim_info *out) {
     out->bytes_mixed[i] = model_bytes(md, 8, 4);
     out->fused_projection[i][0] = md.fuse_proj[0];
     out->fused_projection[i][1] = md.fuse_proj[1];
+    out->planar_z[i] = md.planar_z;
   }
   out->device_bytes = plan->device_bytes;
   return AIM_OK;
@@ -390,11 +396,11 @@ aim_status aim_debug_far_stage(aim_plan *plan, aim_precision prec, int32_t mesh,
     MeshDev &md = plan->mesh[mesh];
     if (prec == AIM_FP64) {
       far_stages<double, double>(plan, md, nrhs, (const double2 *)x + md.offset, plan->n_total,
-                                 stage, s);
+                                 stage, s, nullptr, true);
       copy_far_stage<double>(plan, md, nrhs, stage, grid_out, s);
     } else {
       far_stages<float, float>(plan, md, nrhs, (const float2 *)x + md.offset, plan->n_total, stage,
-                               s);
+                               s, nullptr, true);
       copy_far_stage<float>(plan, md, nrhs, stage, grid_out, s);
     }
   });

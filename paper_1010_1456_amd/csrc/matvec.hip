@@ -250,6 +250,16 @@ const float2 *ghat_of<float>(const MeshDev &md) {
   return md.ghat32;
 }
 template <typename T>
+const cx<T> *ghat2d_of(const MeshDev &md);
+template <>
+const double2 *ghat2d_of<double>(const MeshDev &md) {
+  return md.ghat2d64;
+}
+template <>
+const float2 *ghat2d_of<float>(const MeshDev &md) {
+  return md.ghat2d32;
+}
+template <typename T>
 const cx<T> *tw_of(const MeshDev &md, int d);
 template <>
 const double2 *tw_of<double>(const MeshDev &md, int d) {
@@ -276,7 +286,7 @@ void *work_buffer(Plan *pl, int prec, int which, size_t bytes) {
 
 template <typename T, typename TX>
 void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, int stop,
-                hipStream_t s, hipEvent_t *ev) {
+                hipStream_t s, hipEvent_t *ev, bool full3d) {
   auto mark = [&](int i) {
     if (ev) HIPCHECK(hipEventRecord(ev[i], s));
   };
@@ -288,6 +298,37 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
   const int64_t F = 4 * (int64_t)nrhs;
   const int64_t V0 = (int64_t)Nx * Ny * Nz;
   const int blk = kGridBlock<T>;
+  if (md.planar_z >= 0 && !full3d) {
+    // every source on the plane z = planar_z and only that plane weighted by
+    // the interpolation: 2-D propagation there (y passes straight from and
+    // back to that plane of g0, x pass with the 2-D spectrum); the other
+    // planes of g0 keep the projection's zeros
+    const int64_t V2 = (int64_t)Nx * Py;
+    cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * V0);
+    cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2);
+    const fftk::ContigMap plane = fftk::contig_map(0, 0, (int64_t)Ny * Nz, Nz);
+    mark(0);
+    hipLaunchKernelGGL((k_anterp_gather<T, TX>), dim3((unsigned)((V0 + 255) / 256), nrhs),
+                       dim3(256), 0, s, x, ldx, nrhs, md.node_ptr, md.ent_col, lamT_of<T>(md), g0,
+                       V0);
+    LAUNCHCHECK();
+    mark(1);
+    if (stop <= 1) return;
+    mark(2);
+    fft_pass_contig(g0 + md.planar_z, g2, md.plan[1], Ny, Py, F * Nx, plane, fftk::contig_map(Py),
+                    false, tw_of<T>(md, 1), s);
+    mark(3);
+    if (stop <= 3) return;
+    fft_mid_pass(g2, md.plan[0], Nx, (int)F, Py, 1, md.H[0], md.H[1], 1, ghat2d_of<T>(md),
+                 tw_of<T>(md, 0), 0, V2, s);
+    mark(4);
+    if (stop <= 4) return;
+    fft_pass_contig(g2, g0 + md.planar_z, md.plan[1], Py, Ny, F * Nx, fftk::contig_map(Py), plane,
+                    true, tw_of<T>(md, 1), s);
+    mark(5);
+    mark(6);
+    return;
+  }
   if (thin_layout<T>(Pz)) {
     // few kz (a flat scatterer): kz-outer layouts g1 [F][Pz][Nx][Ny] and
     // g2 [F][Pz][Nx][Py], no row padding; the y lines are contiguous, the x
@@ -474,11 +515,11 @@ void autotune_mesh(Plan *pl, MeshDev &md, hipStream_t s) {
 }
 
 template void far_stages<double, double>(Plan *, MeshDev &, int, const double2 *, int64_t, int,
-                                         hipStream_t, hipEvent_t *);
+                                         hipStream_t, hipEvent_t *, bool);
 template void far_stages<float, float>(Plan *, MeshDev &, int, const float2 *, int64_t, int,
-                                       hipStream_t, hipEvent_t *);
+                                       hipStream_t, hipEvent_t *, bool);
 template void far_stages<float, double>(Plan *, MeshDev &, int, const double2 *, int64_t, int,
-                                        hipStream_t, hipEvent_t *);
+                                        hipStream_t, hipEvent_t *, bool);
 template void matvec_mesh<double, double, double>(Plan *, MeshDev &, int, const double2 *, int64_t,
                                                   double2 *, int64_t, hipStream_t, hipEvent_t *);
 template void matvec_mesh<float, float, float>(Plan *, MeshDev &, int, const float2 *, int64_t,

@@ -123,6 +123,39 @@ __global__ void k_embed_green(double2 *out, int Px, int Py, int Pz, int Nx, int 
   out[t] = v;
 }
 
+// z range of the grid planes holding a non-zero projection weight
+__global__ void k_lam_zrange(const double *lam, const int32_t *anchor3, int64_t n, int M,
+                             int *zr) {
+  const int K = (M + 1) * (M + 1) * (M + 1);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * K) return;
+  const int64_t b = t / K;
+  const int u = (int)(t - b * K);
+  bool nz = false;
+  for (int q = 0; q < 4; ++q) nz |= lam[(b * 4 + q) * K + u] != 0.0;
+  if (!nz) return;
+  const int z = anchor3[3 * b + 2] + u % (M + 1);
+  atomicMin(&zr[0], z);
+  atomicMax(&zr[1], z);
+}
+
+// 2-D spectrum of g(x, y, 0) from the stored 3-D octant: the inverse z
+// transform at z = 0 is the sum over kz, i.e. over the folded kz with
+// multiplicity 2 except kz = 0 and kz = Pz/2 (the normalisation carries over:
+// octant / (Px Py Pz) summed over kz = 2-D spectrum / (Px Py))
+__global__ void k_ghat_zsum(const double2 *oct, double2 *out, int Hx, int Hy, int Hz, int Pz) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)Hx * Hy) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int z = 0; z < Hz; ++z) {
+    const double m = (z == 0 || 2 * z == Pz) ? 1.0 : 2.0;
+    const double2 v = oct[t * Hz + z];
+    acc.x += m * v.x;
+    acc.y += m * v.y;
+  }
+  out[t] = acc;
+}
+
 __global__ void k_extract_octant(const double2 *full, double2 *oct, int Py, int Pz, int Hx, int Hy,
                                  int Hz, double scale) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -393,6 +426,35 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
     HIPCHECK(hipStreamSynchronize(s));
     dev_free(pl, e0);
     dev_free(pl, e1);
+  }
+
+  // a flat scatterer lying in one grid plane: every projection weight on
+  // that plane (exactly: the off-plane Lagrange factors vanish), so the
+  // propagation reduces to the plane (2-D spectrum below)
+  {
+    int zr_h[2] = {INT32_MAX, INT32_MIN};
+    int *zr = upload(pl, zr_h, 2, s);
+    hipLaunchKernelGGL(k_lam_zrange, dim3(blocks_for(n * K, 256)), dim3(256), 0, s, md.lam64,
+                       anchor3, n, M, zr);
+    LAUNCHCHECK();
+    HIPCHECK(hipMemcpyAsync(zr_h, zr, sizeof(zr_h), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    dev_free(pl, zr);
+    md.planar_z = (n > 0 && zr_h[0] == zr_h[1]) ? zr_h[0] : -1;
+    if (md.planar_z >= 0) {
+      const int64_t n2 = (int64_t)md.H[0] * md.H[1];
+      md.ghat2d64 = (double2 *)dev_alloc(pl, sizeof(double2) * n2);
+      hipLaunchKernelGGL(k_ghat_zsum, dim3(blocks_for(n2, 256)), dim3(256), 0, s, md.ghat64,
+                         md.ghat2d64, md.H[0], md.H[1], md.H[2], h.pad[2]);
+      LAUNCHCHECK();
+      if (pl->mixed) {
+        md.ghat2d32 = (float2 *)dev_alloc(pl, sizeof(float2) * n2);
+        hipLaunchKernelGGL(k_to_float, dim3(blocks_for(2 * n2, 256)), dim3(256), 0, s,
+                           (const double *)md.ghat2d64, (float *)md.ghat2d32, 2 * n2);
+        LAUNCHCHECK();
+      }
+      HIPCHECK(hipStreamSynchronize(s));
+    }
   }
 
   // near zone: offsets table size from the largest anchor difference
