@@ -138,17 +138,18 @@ def stage_bytes(info, mesh, nrhs, s_grid, s_real, s_x, s_y, path):
     F = 4 * nrhs
     H = (Px // 2 + 1) * (Py // 2 + 1) * (Pz // 2 + 1)
     lam = n * (4 * K * s_real + 4)
-    if info["planar_z"][mesh] >= 0:  # scatterer in one grid plane: 2-D propagation on it
+    if info["planar_z"][mesh] >= 0:  # scatterer in one grid plane: everything on that plane
         A1, A2 = Nx * Ny, Nx * Py
         H2 = (Px // 2 + 1) * (Py // 2 + 1)
+        lam2 = n * (4 * (info["order"] + 1) ** 2 * s_real + 4)
         return np.array([
-            F * V0 * s_grid + lam + nrhs * n * s_x,
+            F * A1 * s_grid + lam2 + nrhs * n * s_x,
             0.0,
             F * (A1 + A2) * s_grid,
             2 * F * A2 * s_grid + H2 * s_grid,
             F * (A2 + A1) * s_grid,
             0.0,
-            F * V0 * s_grid + lam + nnz * (s_grid + 4) + 4 * (n + 1) + nrhs * n * (s_x + s_y),
+            F * A1 * s_grid + lam2 + nnz * (s_grid + 4) + 4 * (n + 1) + nrhs * n * (s_x + s_y),
         ], dtype=np.float64)
     if info["fused_projection"][mesh][path]:  # projection inside the forward z pass
         proj, fwdz = lam + nrhs * n * s_x + F * V1 * s_grid, 0.0

@@ -141,6 +141,16 @@ struct MeshDev {
   int planar_z = -1;
   double2 *ghat2d64 = nullptr;
   float2 *ghat2d32 = nullptr;
+  // the projection restricted to that plane (plane node p = x Ny + y):
+  // node-ordered entries (ent_col, lamT shared), in-plane stencils of
+  // (M+1)^2 weights, plane-linear anchors and stencil offsets
+  int32_t *plane_node_ptr = nullptr;  // Nx Ny + 1
+  double *plane_lam64 = nullptr;      // n * 4 * (M+1)^2
+  float *plane_lam32 = nullptr;
+  int32_t *plane_anchor = nullptr;    // n
+  int32_t *plane_soff = nullptr;      // (M+1)^2
+  int plane_K = 0;                    // (M+1)^2
+  int plane_npw = 16;                 // plane nodes per wave of the gather
 };
 
 struct Plan;

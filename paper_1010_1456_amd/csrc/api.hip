@@ -90,10 +90,13 @@ static double model_bytes(const MeshDev &md, int sc, int sr) {
   const double V0 = Nx * Ny * Nz, V1 = Nx * Ny * Pz, V2 = Nx * Py * Pz;
   // per field: [projection write V0; z read V0] + z write V1; y: V1 + V2; x: 2 V2;
   // inverse y: V2 + V1; inverse z: V1 + V0; interpolation read V0
-  if (md.planar_z >= 0) {  // per field: projection V0, y passes 2 (Nx Ny + Nx Py), x 2 Nx Py,
-                           // interpolation V0; the 2-D spectrum
-    const double grid = 4.0 * sc * (2.0 * V0 + 2.0 * Nx * Ny + 4.0 * Nx * Py);
-    return vec + lam + nearb + (double)md.H[0] * md.H[1] * sc + grid;
+  if (md.planar_z >= 0) {  // all on the scatterer's plane: per field projection Nx Ny, y
+                           // passes 2 (Nx Ny + Nx Py), x 2 Nx Py, interpolation Nx Ny;
+                           // in-plane stencils; the 2-D spectrum
+    const double K2 = (double)md.plane_K;
+    const double lam2 = 2.0 * n * (4.0 * K2 * sr + 4.0);
+    const double grid = 4.0 * sc * (4.0 * Nx * Ny + 4.0 * Nx * Py);
+    return vec + lam2 + nearb + (double)md.H[0] * md.H[1] * sc + grid;
   }
   const double v0_terms = md.fuse_proj[sc == 16 ? 0 : 1] ? 2.0 : 4.0;
   const double grid = 4.0 * sc * (v0_terms * V0 + 4.0 * V1 + 4.0 * V2);

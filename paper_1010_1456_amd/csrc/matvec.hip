@@ -19,7 +19,8 @@ namespace {
 // Gather form of anterpolation: grid node v sums Lambda_T[e] x_{col[e]} over
 // its entries, so every node (also empty ones) is written exactly once, with
 // no atomics and no clearing pass, in a fixed order (bitwise reproducible).
-// Each 64-lane wave owns 64 consecutive nodes, whose entries are contiguous:
+// Each 64-lane wave owns npw <= 64 consecutive nodes (fewer where nodes hold
+// many entries, so that a wave's entries stay few), whose entries are contiguous:
 // the wave loads them epl * 64 at a time (coalesced; every lane has epl
 // independent gathers in flight), each lane forming its entries' four products
 // in LDS, and every lane then sums the slots of its own node (one right-hand
@@ -34,16 +35,16 @@ template <typename T, typename TX>
 __global__ void __launch_bounds__(256)
     k_anterp_gather(const cx<TX> *__restrict__ x, int64_t ldx, int nrhs,
                     const int32_t *__restrict__ node_ptr, const int32_t *__restrict__ ent_col,
-                    const T *__restrict__ lamT, cx<T> *__restrict__ grid, int64_t V0) {
+                    const T *__restrict__ lamT, cx<T> *__restrict__ grid, int64_t V0, int npw) {
   constexpr int kEpl = anterp_epl<T>();
   constexpr int C = 64 * kEpl;      // entries per chunk
   __shared__ cx<T> slot[4][C][4];  // [wave][entry][q]
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t v0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + w) * 64;
+  const int64_t v0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + w) * npw;
   if (v0 >= V0) return;  // whole wave exits; no block-wide barrier is used
   const int64_t v = v0 + lane;
-  const bool ok = v < V0;
-  const int64_t vend = (v0 + 64 < V0) ? v0 + 64 : V0;
+  const bool ok = lane < npw && v < V0;
+  const int64_t vend = (v0 + npw < V0) ? v0 + npw : V0;
   const int e0 = ok ? node_ptr[v] : 0, e1 = ok ? node_ptr[v + 1] : 0;
   const int w0 = node_ptr[v0], w1 = node_ptr[vend];
   {
@@ -220,6 +221,16 @@ const float *lam_of<float>(const MeshDev &md) {
   return md.lam32;
 }
 template <typename T>
+const T *plane_lam_of(const MeshDev &md);
+template <>
+const double *plane_lam_of<double>(const MeshDev &md) {
+  return md.plane_lam64;
+}
+template <>
+const float *plane_lam_of<float>(const MeshDev &md) {
+  return md.plane_lam32;
+}
+template <typename T>
 const T *lamT_of(const MeshDev &md);
 template <>
 const double *lamT_of<double>(const MeshDev &md) {
@@ -299,23 +310,22 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
   const int64_t V0 = (int64_t)Nx * Ny * Nz;
   const int blk = kGridBlock<T>;
   if (md.planar_z >= 0 && !full3d) {
-    // every source on the plane z = planar_z and only that plane weighted by
-    // the interpolation: 2-D propagation there (y passes straight from and
-    // back to that plane of g0, x pass with the 2-D spectrum); the other
-    // planes of g0 keep the projection's zeros
-    const int64_t V2 = (int64_t)Nx * Py;
-    cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * V0);
+    // every source on the plane z = planar_z, and only that plane weighted by
+    // the interpolation: the plane alone, g0 = [F][Nx][Ny], 2-D propagation
+    // (y passes, x pass with the 2-D spectrum)
+    const int64_t A1 = (int64_t)Nx * Ny, V2 = (int64_t)Nx * Py;
+    cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * A1);
     cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2);
-    const fftk::ContigMap plane = fftk::contig_map(0, 0, (int64_t)Ny * Nz, Nz);
     mark(0);
-    hipLaunchKernelGGL((k_anterp_gather<T, TX>), dim3((unsigned)((V0 + 255) / 256), nrhs),
-                       dim3(256), 0, s, x, ldx, nrhs, md.node_ptr, md.ent_col, lamT_of<T>(md), g0,
-                       V0);
+    hipLaunchKernelGGL((k_anterp_gather<T, TX>),
+                       dim3((unsigned)((A1 + 4 * md.plane_npw - 1) / (4 * md.plane_npw)), nrhs),
+                       dim3(256), 0, s, x, ldx, nrhs, md.plane_node_ptr, md.ent_col,
+                       lamT_of<T>(md), g0, A1, md.plane_npw);
     LAUNCHCHECK();
     mark(1);
     if (stop <= 1) return;
     mark(2);
-    fft_pass_contig(g0 + md.planar_z, g2, md.plan[1], Ny, Py, F * Nx, plane, fftk::contig_map(Py),
+    fft_pass_contig(g0, g2, md.plan[1], Ny, Py, F * Nx, fftk::contig_map(Ny), fftk::contig_map(Py),
                     false, tw_of<T>(md, 1), s);
     mark(3);
     if (stop <= 3) return;
@@ -323,7 +333,7 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
                  tw_of<T>(md, 0), 0, V2, s);
     mark(4);
     if (stop <= 4) return;
-    fft_pass_contig(g2, g0 + md.planar_z, md.plan[1], Py, Ny, F * Nx, fftk::contig_map(Py), plane,
+    fft_pass_contig(g2, g0, md.plan[1], Py, Ny, F * Nx, fftk::contig_map(Py), fftk::contig_map(Ny),
                     true, tw_of<T>(md, 1), s);
     mark(5);
     mark(6);
@@ -340,7 +350,7 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     mark(0);
     hipLaunchKernelGGL((k_anterp_gather<T, TX>), dim3((unsigned)((V0 + 255) / 256), nrhs),
                        dim3(256), 0, s, x, ldx, nrhs, md.node_ptr, md.ent_col, lamT_of<T>(md), g0,
-                       V0);
+                       V0, 64);
     LAUNCHCHECK();
     mark(1);
     if (stop <= 1) return;
@@ -384,7 +394,7 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
                    Pzs, (int64_t)Nx * Ny * Pzs, tw_of<T>(md, 2), md.plan[2], s)) {
     hipLaunchKernelGGL((k_anterp_gather<T, TX>), dim3((unsigned)((V0 + 255) / 256), nrhs),
                        dim3(256), 0, s, x, ldx, nrhs, md.node_ptr, md.ent_col, lamT_of<T>(md), g0,
-                       V0);
+                       V0, 64);
     LAUNCHCHECK();
     mark(1);
     if (stop <= 1) return;
@@ -417,11 +427,15 @@ void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, 
   const int prec = sizeof(T) == 8 ? 0 : 1;
   far_stages<T, TX>(pl, md, nrhs, x, ldx, 6, s, ev);
   const cx<T> *phi = (const cx<T> *)pl->work[prec][0];
-  const int64_t V0 = (int64_t)h.grid[0] * h.grid[1] * h.grid[2];
+  const bool plane = md.planar_z >= 0;  // fields on the scatterer's grid plane only
+  const int64_t V0 = plane ? (int64_t)h.grid[0] * h.grid[1]
+                           : (int64_t)h.grid[0] * h.grid[1] * h.grid[2];
   const int rows_per_block = 8;
   const int64_t blocks = (h.n + rows_per_block - 1) / rows_per_block;
   hipLaunchKernelGGL((k_interp_near<T, TX, TY>), dim3((unsigned)blocks, nrhs), dim3(32 * rows_per_block),
-                     0, s, phi, V0, nrhs, lam_of<T>(md), md.anchor_lin, md.stencil_off, h.K,
+                     0, s, phi, V0, nrhs, plane ? plane_lam_of<T>(md) : lam_of<T>(md),
+                     plane ? md.plane_anchor : md.anchor_lin,
+                     plane ? md.plane_soff : md.stencil_off, plane ? md.plane_K : h.K,
                      md.rowptr, md.cols, near_of<T>(md), x, ldx, y, ldy, h.n,
                      (T)(h.k * kEta0), (T)(1.0 / (h.k * h.k)));
   LAUNCHCHECK();

@@ -139,6 +139,20 @@ __global__ void k_lam_zrange(const double *lam, const int32_t *anchor3, int64_t 
   atomicMax(&zr[1], z);
 }
 
+// in-plane weights: plane_lam[b][q][ui (M+1) + uj] = lam[b][q][u] with u's
+// z index on the plane
+__global__ void k_lam_plane(const double *lam, const int32_t *anchor3, int64_t n, int M, int zp,
+                            double *plane_lam) {
+  const int K = (M + 1) * (M + 1) * (M + 1), K2 = (M + 1) * (M + 1);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * K2) return;
+  const int64_t b = t / K2;
+  const int u2 = (int)(t - b * K2);
+  const int uk = zp - anchor3[3 * b + 2];  // in 0..M: the plane holds the basis' weights
+  for (int q = 0; q < 4; ++q)
+    plane_lam[(b * 4 + q) * K2 + u2] = lam[(b * 4 + q) * K + u2 * (M + 1) + uk];
+}
+
 // 2-D spectrum of g(x, y, 0) from the stored 3-D octant: the inverse z
 // transform at z = 0 is the sum over kz, i.e. over the folded kz with
 // multiplicity 2 except kz = 0 and kz = Pz/2 (the normalisation carries over:
@@ -352,6 +366,41 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
     LAUNCHCHECK();
   }
 
+  // a flat scatterer lying in one grid plane: every projection weight on
+  // that plane (exactly: the off-plane Lagrange factors vanish), so the
+  // propagation and the interpolation reduce to the plane
+  {
+    int zr_h[2] = {INT32_MAX, INT32_MIN};
+    int *zr = upload(pl, zr_h, 2, s);
+    hipLaunchKernelGGL(k_lam_zrange, dim3(blocks_for(n * K, 256)), dim3(256), 0, s, md.lam64,
+                       anchor3, n, M, zr);
+    LAUNCHCHECK();
+    HIPCHECK(hipMemcpyAsync(zr_h, zr, sizeof(zr_h), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    dev_free(pl, zr);
+    md.planar_z = (n > 0 && zr_h[0] == zr_h[1]) ? zr_h[0] : -1;
+  }
+  if (md.planar_z >= 0) {
+    // in-plane stencils: (M+1)^2 weights per component, plane-linear anchors
+    const int K2 = (M + 1) * (M + 1);
+    md.plane_lam64 = (double *)dev_alloc(pl, sizeof(double) * n * 4 * K2);
+    hipLaunchKernelGGL(k_lam_plane, dim3(blocks_for(n * K2, 256)), dim3(256), 0, s, md.lam64,
+                       anchor3, n, M, md.planar_z, md.plane_lam64);
+    LAUNCHCHECK();
+    if (pl->mixed) {
+      md.plane_lam32 = (float *)dev_alloc(pl, sizeof(float) * n * 4 * K2);
+      hipLaunchKernelGGL(k_to_float, dim3(blocks_for(n * 4 * K2, 256)), dim3(256), 0, s,
+                         md.plane_lam64, md.plane_lam32, n * 4 * K2);
+      LAUNCHCHECK();
+    }
+    std::vector<int32_t> a2(n), so2(K2);
+    for (int64_t i = 0; i < n; ++i) a2[i] = h.anchor[3 * i] * h.grid[1] + h.anchor[3 * i + 1];
+    for (int u = 0; u < K2; ++u) so2[u] = (u / (M + 1)) * h.grid[1] + u % (M + 1);
+    md.plane_anchor = upload(pl, a2.data(), a2.size(), s);
+    md.plane_soff = upload(pl, so2.data(), so2.size(), s);
+    md.plane_K = K2;
+  }
+
   // node-ordered (transposed) projection for the gather form of anterpolation
   {
     const int64_t NK = n * K;
@@ -381,6 +430,13 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
         }
     md.n_entries = ne;
     md.node_ptr = upload(pl, ptr.data(), ptr.size(), s);
+    if (md.planar_z >= 0) {  // all entries sit on the plane: plane node p = x Ny + y
+      const int64_t A = (int64_t)h.grid[0] * h.grid[1];
+      std::vector<int32_t> p2(A + 1);
+      for (int64_t p = 0; p < A; ++p) p2[p] = ptr[p * h.grid[2] + md.planar_z];
+      p2[A] = ptr[V0];
+      md.plane_node_ptr = upload(pl, p2.data(), p2.size(), s);
+    }
     md.ent_col = upload(pl, col.data(), col.size(), s);
     int32_t *dsrc = upload(pl, src.data(), src.size(), s);
     md.lamT64 = (double *)dev_alloc(pl, sizeof(double) * 4 * std::max<int64_t>(ne, 1));
@@ -427,34 +483,19 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
     dev_free(pl, e0);
     dev_free(pl, e1);
   }
-
-  // a flat scatterer lying in one grid plane: every projection weight on
-  // that plane (exactly: the off-plane Lagrange factors vanish), so the
-  // propagation reduces to the plane (2-D spectrum below)
-  {
-    int zr_h[2] = {INT32_MAX, INT32_MIN};
-    int *zr = upload(pl, zr_h, 2, s);
-    hipLaunchKernelGGL(k_lam_zrange, dim3(blocks_for(n * K, 256)), dim3(256), 0, s, md.lam64,
-                       anchor3, n, M, zr);
+  if (md.planar_z >= 0) {
+    const int64_t n2 = (int64_t)md.H[0] * md.H[1];
+    md.ghat2d64 = (double2 *)dev_alloc(pl, sizeof(double2) * n2);
+    hipLaunchKernelGGL(k_ghat_zsum, dim3(blocks_for(n2, 256)), dim3(256), 0, s, md.ghat64,
+                       md.ghat2d64, md.H[0], md.H[1], md.H[2], h.pad[2]);
     LAUNCHCHECK();
-    HIPCHECK(hipMemcpyAsync(zr_h, zr, sizeof(zr_h), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
-    dev_free(pl, zr);
-    md.planar_z = (n > 0 && zr_h[0] == zr_h[1]) ? zr_h[0] : -1;
-    if (md.planar_z >= 0) {
-      const int64_t n2 = (int64_t)md.H[0] * md.H[1];
-      md.ghat2d64 = (double2 *)dev_alloc(pl, sizeof(double2) * n2);
-      hipLaunchKernelGGL(k_ghat_zsum, dim3(blocks_for(n2, 256)), dim3(256), 0, s, md.ghat64,
-                         md.ghat2d64, md.H[0], md.H[1], md.H[2], h.pad[2]);
+    if (pl->mixed) {
+      md.ghat2d32 = (float2 *)dev_alloc(pl, sizeof(float2) * n2);
+      hipLaunchKernelGGL(k_to_float, dim3(blocks_for(2 * n2, 256)), dim3(256), 0, s,
+                         (const double *)md.ghat2d64, (float *)md.ghat2d32, 2 * n2);
       LAUNCHCHECK();
-      if (pl->mixed) {
-        md.ghat2d32 = (float2 *)dev_alloc(pl, sizeof(float2) * n2);
-        hipLaunchKernelGGL(k_to_float, dim3(blocks_for(2 * n2, 256)), dim3(256), 0, s,
-                           (const double *)md.ghat2d64, (float *)md.ghat2d32, 2 * n2);
-        LAUNCHCHECK();
-      }
-      HIPCHECK(hipStreamSynchronize(s));
     }
+    HIPCHECK(hipStreamSynchronize(s));
   }
 
   // near zone: offsets table size from the largest anchor difference
