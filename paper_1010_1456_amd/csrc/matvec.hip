@@ -141,7 +141,9 @@ __device__ __forceinline__ V half_wave_sum(V v) {
 //       + sum_n Z^near_mn x_n. One 32-lane half-wave per row m.
 constexpr int kNearUnroll = 4;
 
-template <typename T, typename TX, typename TY>
+// RB right-hand sides per grid row (blockIdx.y): the stencil weights, the
+// near-zone entries and their columns are loaded once for the RB products
+template <typename T, typename TX, typename TY, int RB>
 __global__ void __launch_bounds__(256)
     k_interp_near(const cx<T> *__restrict__ phi, int64_t V0, int nrhs, const T *__restrict__ lam,
                   const int32_t *__restrict__ anchor_lin, const int32_t *__restrict__ soff, int K,
@@ -154,58 +156,62 @@ __global__ void __launch_bounds__(256)
   if (m >= n) return;  // both rows of a wave exit together or each half runs alone
   const int64_t a = anchor_lin[m];
   const int e0 = rowptr[m], e1 = rowptr[m + 1];
-  {
-    const int r = blockIdx.y;  // right-hand side
-    V far;
-    far.x = 0;
-    far.y = 0;
-    const V *ph = phi + (int64_t)(r * 4) * V0 + a;
-    for (int u = lane; u < K; u += 32) {
-      const int64_t o = soff[u];
-      const T l0 = lam[(m * 4 + 0) * K + u], l1 = lam[(m * 4 + 1) * K + u];
-      const T l2 = lam[(m * 4 + 2) * K + u], l3 = lam[(m * 4 + 3) * K + u];
-      const V p0 = ph[o], p1 = ph[V0 + o], p2 = ph[2 * V0 + o], p3 = ph[3 * V0 + o];
-      far.x += l0 * p0.x + l1 * p1.x + l2 * p2.x - inv_k2 * l3 * p3.x;
-      far.y += l0 * p0.y + l1 * p1.y + l2 * p2.y - inv_k2 * l3 * p3.y;
-    }
-    V nr;
-    nr.x = 0;
-    nr.y = 0;
-    const cx<TX> *xr = x + (int64_t)r * ldx;
-    // kNearUnroll entries per lane per pass, all gathers issued before any
-    // is used (rows hold ~80 entries: one pass of dependent loads, not three)
-    for (int eb = e0 + lane; eb < e1; eb += 32 * kNearUnroll) {
-      V z[kNearUnroll];
-      int c[kNearUnroll];
+  const int r0 = blockIdx.y * RB;  // first right-hand side of this row
+  V far[RB], nr[RB];
 #pragma unroll
-      for (int k = 0; k < kNearUnroll; ++k) {
-        const int e = eb + 32 * k;
-        const bool in = e < e1;
-        c[k] = in ? cols[e] : 0;
-        if (in) {
-          z[k] = nearv[e];
-        } else {
-          z[k].x = 0;
-          z[k].y = 0;
-        }
+  for (int rb = 0; rb < RB; ++rb) far[rb].x = far[rb].y = nr[rb].x = nr[rb].y = 0;
+  for (int u = lane; u < K; u += 32) {
+    const int64_t o = a + soff[u];
+    const T l0 = lam[(m * 4 + 0) * K + u], l1 = lam[(m * 4 + 1) * K + u];
+    const T l2 = lam[(m * 4 + 2) * K + u], l3 = lam[(m * 4 + 3) * K + u];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const V *ph = phi + (int64_t)((r0 + rb) * 4) * V0 + o;
+      const V p0 = ph[0], p1 = ph[V0], p2 = ph[2 * V0], p3 = ph[3 * V0];
+      far[rb].x += l0 * p0.x + l1 * p1.x + l2 * p2.x - inv_k2 * l3 * p3.x;
+      far[rb].y += l0 * p0.y + l1 * p1.y + l2 * p2.y - inv_k2 * l3 * p3.y;
+    }
+  }
+  // kNearUnroll entries per lane per pass, all gathers issued before any is
+  // used (rows hold ~80 entries: one pass of dependent loads, not three)
+  for (int eb = e0 + lane; eb < e1; eb += 32 * kNearUnroll) {
+    V z[kNearUnroll];
+    int c[kNearUnroll];
+#pragma unroll
+    for (int k = 0; k < kNearUnroll; ++k) {
+      const int e = eb + 32 * k;
+      const bool in = e < e1;
+      c[k] = in ? cols[e] : 0;
+      if (in) {
+        z[k] = nearv[e];
+      } else {
+        z[k].x = 0;
+        z[k].y = 0;
       }
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      const cx<TX> *xr = x + (int64_t)(r0 + rb) * ldx;
 #pragma unroll
       for (int k = 0; k < kNearUnroll; ++k) {
         const cx<TX> xv = xr[c[k]];
         const T xa = (T)xv.x, xb = (T)xv.y;
-        nr.x += z[k].x * xa - z[k].y * xb;
-        nr.y += z[k].x * xb + z[k].y * xa;
+        nr[rb].x += z[k].x * xa - z[k].y * xb;
+        nr[rb].y += z[k].x * xb + z[k].y * xa;
       }
     }
+  }
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
     V acc;
-    acc.x = -keta * far.y + nr.x;  // j k eta * far
-    acc.y = keta * far.x + nr.y;
+    acc.x = -keta * far[rb].y + nr[rb].x;  // j k eta * far
+    acc.y = keta * far[rb].x + nr[rb].y;
     acc = half_wave_sum(acc);
     if (lane == 0) {
       cx<TY> out;
       out.x = (decltype(out.x))acc.x;
       out.y = (decltype(out.y))acc.y;
-      y[(int64_t)r * ldy + m] = out;
+      y[(int64_t)(r0 + rb) * ldy + m] = out;
     }
   }
 }
@@ -432,12 +438,22 @@ void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, 
                            : (int64_t)h.grid[0] * h.grid[1] * h.grid[2];
   const int rows_per_block = 8;
   const int64_t blocks = (h.n + rows_per_block - 1) / rows_per_block;
-  hipLaunchKernelGGL((k_interp_near<T, TX, TY>), dim3((unsigned)blocks, nrhs), dim3(32 * rows_per_block),
-                     0, s, phi, V0, nrhs, plane ? plane_lam_of<T>(md) : lam_of<T>(md),
-                     plane ? md.plane_anchor : md.anchor_lin,
-                     plane ? md.plane_soff : md.stencil_off, plane ? md.plane_K : h.K,
-                     md.rowptr, md.cols, near_of<T>(md), x, ldx, y, ldy, h.n,
-                     (T)(h.k * kEta0), (T)(1.0 / (h.k * h.k)));
+  // right-hand sides per grid row: 4 or 2 when they divide nrhs
+  const int rb = nrhs % 4 == 0 ? 4 : (nrhs % 2 == 0 ? 2 : 1);
+  auto launch = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks, nrhs / rb), dim3(32 * rows_per_block), 0, s,
+                       phi, V0, nrhs, plane ? plane_lam_of<T>(md) : lam_of<T>(md),
+                       plane ? md.plane_anchor : md.anchor_lin,
+                       plane ? md.plane_soff : md.stencil_off, plane ? md.plane_K : h.K,
+                       md.rowptr, md.cols, near_of<T>(md), x, ldx, y, ldy, h.n,
+                       (T)(h.k * kEta0), (T)(1.0 / (h.k * h.k)));
+  };
+  if (rb == 4)
+    launch(k_interp_near<T, TX, TY, 4>);
+  else if (rb == 2)
+    launch(k_interp_near<T, TX, TY, 2>);
+  else
+    launch(k_interp_near<T, TX, TY, 1>);
   LAUNCHCHECK();
   if (ev) HIPCHECK(hipEventRecord(ev[7], s));
 }
