@@ -1,0 +1,50 @@
+"""The small DFTs of the FFT passes, built for the host from the same header
+(fft_core.h), against numpy's FFT: every supported radix, both directions,
+including the prime-factor (coprime) splits and the upper-half-zero DFT used
+by the pruned first stage. CPU only (hipcc compiles the host side)."""
+
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "..", "paper_1010_1456_amd", "csrc")
+
+
+def _hipcc():
+    for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if c and os.path.exists(c):
+            return c
+    pytest.skip("hipcc not available")
+
+
+@pytest.fixture(scope="module")
+def lines():
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "fft_blocks")
+        subprocess.run([_hipcc(), "-O1", "-std=c++17", "-x", "hip", "--offload-arch=gfx950",
+                        "-I", CSRC, os.path.join(HERE, "fft_blocks_check.cpp"), "-o", exe],
+                       check=True, capture_output=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    rows = {}
+    for ln in out.splitlines():
+        R, inv, uz, k, re, im = ln.split()
+        rows.setdefault((int(R), int(inv), int(uz)), {})[int(k)] = complex(float(re), float(im))
+    return rows
+
+
+def test_every_radix_and_direction(lines):
+    radices = sorted({k[0] for k in lines})
+    assert radices == [2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 14, 16, 18]
+    for (R, inv, uz), got in lines.items():
+        i = np.arange(R)
+        x = np.sin(1.3 * i + 0.2) + 1j * np.cos(0.7 * i * i)
+        if uz:
+            x[R // 2:] = 0
+        ref = np.fft.ifft(x) * R if inv else np.fft.fft(x)
+        g = np.array([got[k] for k in range(R)])
+        assert np.abs(g - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()), (R, inv, uz)
