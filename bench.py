@@ -54,11 +54,18 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# sources that define the product's kernels, their launches and the layout of
+# the operator data they read (the solver, RCS, ABI glue, host planning and
+# near-field quadrature do not change a product kernel's memory traffic)
+MATVEC_SOURCES_EXCLUDED = ("api.hip", "solver.hip", "rcs.hip", "host_plan.cpp", "geom_device.h")
+
+
 def sources_digest():
-    """Digest of the kernel sources: HBM counters taken on other sources are stale."""
+    """Digest of the product's kernel sources: HBM counters taken on other
+    sources are stale."""
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".h", ".hip", ".cpp")):
+        if name.endswith((".h", ".hip", ".cpp")) and name not in MATVEC_SOURCES_EXCLUDED:
             with open(os.path.join(CSRC, name), "rb") as f:
                 h.update(name.encode())
                 h.update(f.read())
@@ -167,6 +174,43 @@ def stage_bytes(info, mesh, nrhs, s_grid, s_real, s_x, s_y, path):
     ], dtype=np.float64)
 
 
+def fill_report(info):
+    """Set-up (matrix fill) phase times of the plan, summed over scatterers,
+    and the near-zone fill rate: FP64 entries of Z^MOM - Z^grid per second."""
+    ph = {k: float(sum(d[k] for d in info["setup_ms"])) for k in info["setup_ms"][0]}
+    out = {f"{k}_ms": v for k, v in ph.items()}
+    out["near_entries"] = int(info["nnz_total"])
+    out["near_entries_per_s"] = info["nnz_total"] / (ph["near_fill"] * 1e-3) if ph["near_fill"] > 0 else None
+    return out
+
+
+def cpu_fill_baseline(cfg, freq_hz):
+    """The oracle's near-zone fill (Z^MOM on the pattern, then Z^grid) on a
+    half-wavelength-radius sphere meshed at the workload's density: FP64
+    entries per second on one host core (numpy)."""
+    from oracle import aim as oaim
+    from oracle import mom as omom
+    from oracle.constants import wavenumber
+    from oracle.rwg import build_rwg
+    from workloads import sphere_mesh
+
+    m = sphere_mesh(0.5, freq_hz)
+    rwg = build_rwg(m.verts, m.tris)
+    k = wavenumber(freq_hz)
+    grid = oaim.grid_plan(rwg.verts, cfg["h_lambda"] * m.lam, cfg["order"])
+    anc = oaim.anchors(grid, rwg.centre)
+    lam = oaim.projection(rwg, grid, anc)
+    indptr, indices = oaim.near_pairs(rwg.centre, cfg["near_radius_lambda"] * m.lam)
+    rows = np.repeat(np.arange(rwg.n), np.diff(indptr))
+    t0 = time.perf_counter()
+    omom.sparse_z(rwg, k, indptr, indices)
+    oaim.zgrid_entries(k, grid, lam, anc, rows, indices)
+    dt = time.perf_counter() - t0
+    return {"near_entries_per_s": indices.shape[0] / dt, "seconds": dt, "cores": 1, "kind": "oracle",
+            "sample": (f"near-zone fill of a 0.5-lambda-radius sphere (N={rwg.n}, {indices.shape[0]} "
+                       f"entries, M={cfg['order']}) by oracle.mom.sparse_z and oracle.aim.zgrid_entries")}
+
+
 def time_path(plan, A, prec, x, y, steps, warmup):
     import torch
 
@@ -265,6 +309,81 @@ def solve_compare(plan, A, mesh, workload, iters):
     return out
 
 
+def accuracy_sweep(A, max_iter):
+    """err_tt of AIM solutions against references, the form of the paper's
+    Tables 1-2 err columns (Section 2.2) with this library's parameters: a
+    4-lambda plate (EFIE) and a 1-lambda-radius sphere at 0.3 GHz, x-polarised
+    wave toward -z, 2-degree RCS grid. References: the classical MOM solution
+    (every basis pair in the near zone, so the product is Z^MOM), the
+    fifth-order AIM (the paper's reference where MOM is too costly) and, for
+    the sphere, the Mie series. Candidates sweep the stencil order M, the
+    near-zone size gamma (in grid spacings) and the grid spacing h."""
+    import torch
+
+    from oracle import farfield as off
+    from oracle import mie as omie
+    from oracle.constants import wavenumber
+    from workloads import plate_mesh, sphere_mesh
+
+    th, ph = off.rcs_grid(2.0)
+    wave = [(0.0, 0.0, 0)]
+    f = 0.3e9
+    scatterers = [("plate4", plate_mesh(4.0, f), None), ("sphere1", sphere_mesh(1.0, f), 1.0)]
+    out = {"setting": "GMRES(100), right Jacobi; candidates tol 1e-4, references tol 1e-8; "
+                      "err_tt per eq. (1) over a 2-degree (theta, phi) grid", "scatterers": []}
+    for name, m, radius in scatterers:
+        ext = np.ptp(m.verts, axis=0)
+        r_all = 1.01 * float(np.linalg.norm(ext)) / m.lam + 0.05  # every pair near
+
+        def run(order, h, near_lambda, prec, tol):
+            t0 = time.perf_counter()
+            plan = A.Plan([(m.verts, m.tris, m.freq_hz)], h_lambda=h, order=order,
+                          near_radius_lambda=near_lambda)
+            torch.cuda.synchronize()
+            setup = time.perf_counter() - t0
+            plan.solve(wave, prec, tol=tol, restart=100, max_iter=2, raise_on_noconv=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, st = plan.solve(wave, prec, tol=tol, restart=100, max_iter=max_iter,
+                               raise_on_noconv=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            sig = plan.rcs(x, th, ph)[0, 0]
+            info = plan.info()
+            plan.close()
+            return sig, dict(n=int(info["n_total"]), grid=[int(v) for v in info["grid"][0]],
+                             nnz=int(info["nnz_total"]), setup_s=setup, iterations=st[0]["iterations"],
+                             converged=bool(st[0]["converged"]), residual=float(st[0]["residual"]),
+                             solve_s=dt)
+
+        log(f"[sweep] {name}: references")
+        refs, ref_meta = {}, {}
+        refs["mom"], ref_meta["mom"] = run(2, 0.1, r_all, A.AIM_FP64, 1e-8)
+        refs["aim_m5"], ref_meta["aim_m5"] = run(5, 0.1, 0.5, A.AIM_FP64, 1e-8)
+        if radius is not None:
+            refs["mie"] = omie.sigma_tt(wavenumber(f), radius * m.lam, th, ph)
+        ref_meta["aim_m5"]["params"] = "M=5, h=0.1 lambda, gamma=5"
+        ref_meta["aim_m5"]["err_vs"] = {k: off.err_tt(refs["aim_m5"], v, th)
+                                        for k, v in refs.items() if k != "aim_m5"}
+        ref_meta["mom"]["err_vs"] = {k: off.err_tt(refs["mom"], v, th)
+                                     for k, v in refs.items() if k not in ("mom", "aim_m5")}
+        cand = [(M, 0.1, 3.0, p) for M in (1, 2, 3, 4, 5) for p in ("mixed", "fp64")]
+        cand += [(2, 0.1, g, "mixed") for g in (2.0, 4.0, 5.0)]
+        cand += [(2, hh, 3.0, "mixed") for hh in (0.075, 0.125, 0.15)]
+        cand += [(3, 0.1, 4.0, "mixed"), (4, 0.1, 5.0, "mixed")]
+        rows = []
+        for M, hh, g, p in cand:
+            prec = A.AIM_MIXED if p == "mixed" else A.AIM_FP64
+            sig, meta = run(M, hh, g * hh, prec, 1e-4)
+            meta.update(M=M, h_lambda=hh, gamma=g, precision=p,
+                        err_vs={k: off.err_tt(sig, v, th) for k, v in refs.items()})
+            rows.append(meta)
+            log(f"[sweep] {name} M={M} h={hh} gamma={g} {p}: its {meta['iterations']}, "
+                + ", ".join(f"err vs {k} {v:.2e}" for k, v in meta["err_vs"].items()))
+        out["scatterers"].append(dict(name=name, references=ref_meta, rows=rows))
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,12 +393,17 @@ def main(argv=None):
                     choices=["sphere8", "plate16", "plate1", "plate128", "batch6"])
     ap.add_argument("--nrhs", type=int, default=None,
                     help="right-hand sides per scatterer (default 1; 16 for batch6)")
+    ap.add_argument("--order", type=int, default=None,
+                    help="stencil order M (default: the workload's, 2)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--solve-iters", type=int, default=300,
                     help="GMRES iteration budget of the solve comparison (0 skips it)")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run a plain elementwise copy of 256 MiB (3 launches) whose "
                          "FETCH_SIZE/WRITE_SIZE counters calibrate the HBM byte counts")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the throughput line, print the accuracy/parameter sweep "
+                         "(err_tt against MOM, fifth-order AIM and Mie references) as one JSON line")
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn the counter_collection.csv of a FETCH_SIZE and a WRITE_SIZE "
                          "rocprofv3 run of `bench.py --calibrate` into "
@@ -299,6 +423,9 @@ def main(argv=None):
     from paper_1010_1456_amd import aim as A
     from workloads import CONFIGS, config_mesh, config_meshes, random_current
 
+    if args.sweep:
+        print(json.dumps(accuracy_sweep(A, 3000)), flush=True)
+        return
     if args.calibrate:
         a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -306,7 +433,9 @@ def main(argv=None):
             torch.mul(a, 1.0, out=b)  # reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
         del a, b
-    cfg = CONFIGS[args.workload]
+    cfg = dict(CONFIGS[args.workload])
+    if args.order is not None:
+        cfg["order"] = args.order
     log(f"[bench] meshing {args.workload}")
     meshes = config_meshes(args.workload)
     mesh = meshes[0]
@@ -362,7 +491,8 @@ def main(argv=None):
                 "plate128": "PEC plate 128 lambda at 38.4 GHz, 1152x1152 squares",
                 "batch6": "6 scatterers in one plan at 0.3 GHz: PEC plates 2, 4, 8 lambda and spheres "
                           "1, 2, 4 lambda (seeded vertex jitter), R right-hand sides each",
-            }[args.workload] + f"; EFIE-AIM h=0.1 lambda, M=2 (27-node stencils), near radius 0.3 lambda; "
+            }[args.workload] + f"; EFIE-AIM h={cfg['h_lambda']} lambda, M={cfg['order']} ({(cfg['order'] + 1) ** 3}-node "
+                               f"stencils), near radius {cfg['near_radius_lambda']} lambda; "
                                f"N={n}, grid {info['grid'] if info['nmesh'] > 1 else info['grid'][0]}, "
                                f"FFT {info['pad'] if info['nmesh'] > 1 else info['pad'][0]}, "
                                f"near nnz {info['nnz_total']}; nrhs={R}"),
@@ -399,6 +529,7 @@ def main(argv=None):
         },
         "mixed_over_fp64": res["fp64"]["wall"] / mx["wall"],
         "setup_s": setup_s,
+        "fill": fill_report(info),
         "device_bytes": info["device_bytes"],
     }
     if args.solve_iters > 0:
@@ -406,6 +537,7 @@ def main(argv=None):
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(mesh, cfg, R, tuple(info["pad"][0]))
+        out["fill"]["cpu_oracle"] = cpu_fill_baseline(cfg, mesh.freq_hz)
     print(json.dumps(out), flush=True)
     plan.close()
 

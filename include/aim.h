@@ -74,8 +74,10 @@ typedef struct {
 /* AIM parameters (paper Section 2.2 sets the moment-matching order and the
  * near-zone size gamma; grid spacing is chosen empirically there).
  * h_lambda            grid spacing in wavelengths (> 0), e.g. 0.1
- * order               stencil order M >= 1: (M+1)^3 nodes, moments matched
- *                     up to order M in each coordinate, e.g. 2
+ * order               stencil order M in 1..5: (M+1)^3 nodes, moments matched
+ *                     up to order M in each coordinate, e.g. 2 (the paper
+ *                     matches up to fifth order for its reference solutions,
+ *                     Section 2.2); other values give AIM_ERR_ARG
  * near_radius_lambda  near zone: basis pairs whose centres are within this
  *                     distance (wavelengths, >= 0), e.g. 0.3 (= 3 h)
  * fft_min_pad         0: FFT length per dimension = smallest supported
@@ -118,6 +120,14 @@ typedef struct {
  * bytes of one single-RHS product in each precision: operator data read once,
  * vectors read/written once, grid traffic of the pruned pass structure used
  * (with fused_projection, the projected grid is never stored). */
+/* set-up phases timed in aim_info.setup_ms */
+#define AIM_NSETUP 5
+#define AIM_SETUP_HOST_PLAN 0
+#define AIM_SETUP_PROJECTION 1
+#define AIM_SETUP_GREEN 2
+#define AIM_SETUP_NEAR_FILL 3
+#define AIM_SETUP_TUNE 4
+
 typedef struct {
   int32_t nmesh;
   int32_t order;
@@ -141,6 +151,12 @@ typedef struct {
                                            grid plane), else -1; the propagation then runs
                                            on that plane alone with the 2-D spectrum */
   double device_bytes;                  /* device memory held by the plan */
+  double setup_ms[AIM_MAX_MESH][AIM_NSETUP]; /* wall time of each set-up phase, ms: host plan
+                                               (mesh checks, RWG table, grid, anchors, near-zone
+                                               pattern), projection weights, Green's spectrum,
+                                               near-zone fill (FP64 quadrature of Z^MOM - Z^grid),
+                                               variant tuning (paper Section 2.4, Fig. 4, times
+                                               the matrix fill) */
 } aim_info;
 
 /* GMRES options. restart m (<= 200), relative-residual tolerance on

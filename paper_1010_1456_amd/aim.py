@@ -35,6 +35,9 @@ AIM_DATA_LAMBDA64 = 1
 AIM_DATA_NEAR64 = 2
 AIM_DATA_ZDIAG64 = 3
 AIM_DATA_GHAT64 = 4
+AIM_NSETUP = 5
+# set-up phases of aim_info.setup_ms, in order
+SETUP_PHASES = ("host_plan", "projection", "green", "near_fill", "tune")
 
 EXPORTED = [
     "aim_setup", "aim_plan_info", "aim_destroy", "aim_matvec", "aim_matvec_timed", "aim_gmres_solve",
@@ -79,7 +82,7 @@ class AimInfo(ctypes.Structure):
                 ("h", c_double * M), ("x0", (c_double * 3) * M), ("k", c_double * M),
                 ("bytes_fp64", c_double * M), ("bytes_mixed", c_double * M),
                 ("fused_projection", (c_int32 * 2) * M), ("planar_z", c_int32 * M),
-                ("device_bytes", c_double)]
+                ("device_bytes", c_double), ("setup_ms", (c_double * AIM_NSETUP) * M)]
 
 
 class AimSolveOpts(ctypes.Structure):
@@ -273,7 +276,8 @@ class Plan:
             fused_projection=[(bool(inf.fused_projection[i][0]), bool(inf.fused_projection[i][1]))
                               for i in range(nm)],
             planar_z=[inf.planar_z[i] for i in range(nm)],
-            device_bytes=inf.device_bytes)
+            device_bytes=inf.device_bytes,
+            setup_ms=[dict(zip(SETUP_PHASES, inf.setup_ms[i])) for i in range(nm)])
 
     def _stream(self, stream):
         s = stream if stream is not None else self._torch.cuda.current_stream()

@@ -151,7 +151,11 @@ struct MeshDev {
   int32_t *plane_soff = nullptr;      // (M+1)^2
   int plane_K = 0;                    // (M+1)^2
   int plane_npw = 16;                 // plane nodes per wave of the gather
+  double setup_ms[AIM_NSETUP] = {0, 0, 0, 0, 0};  // wall time per set-up phase
 };
+
+// milliseconds since an arbitrary epoch (steady clock)
+double wall_ms();
 
 struct Plan;
 

@@ -16,6 +16,11 @@ void hip_check(hipError_t e, const char *what, const char *file, int line) {
                                  std::to_string(line) + ")");
 }
 
+double wall_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
 void *dev_alloc(Plan *pl, size_t bytes) {
   if (bytes == 0) bytes = 256;
   void *p = nullptr;
@@ -175,14 +180,21 @@ aim_status aim_setup(const aim_mesh *meshes, int32_t nmesh, const aim_params *p,
   aim_status st = guarded([&] {
     int64_t off = 0;
     for (int i = 0; i < nmesh; ++i) {
+      const double t0 = wall_ms();
       host_plan_build(meshes[i], *p, &pl->mesh[i].hp);
+      pl->mesh[i].setup_ms[AIM_SETUP_HOST_PLAN] = wall_ms() - t0;
       pl->mesh[i].offset = off;
       off += pl->mesh[i].hp.n;
     }
     pl->n_total = off;
     if (off > INT32_MAX) throw Error(AIM_ERR_ARG, "too many unknowns");
     for (int i = 0; i < nmesh; ++i) setup_mesh_device(pl.get(), pl->mesh[i], pl->setup_stream);
-    for (int i = 0; i < nmesh; ++i) autotune_mesh(pl.get(), pl->mesh[i], pl->setup_stream);
+    for (int i = 0; i < nmesh; ++i) {
+      const double t0 = wall_ms();
+      autotune_mesh(pl.get(), pl->mesh[i], pl->setup_stream);
+      HIPCHECK(hipStreamSynchronize(pl->setup_stream));
+      pl->mesh[i].setup_ms[AIM_SETUP_TUNE] = wall_ms() - t0;
+    }
     HIPCHECK(hipStreamSynchronize(pl->setup_stream));
   });
   if (st != AIM_OK) {
@@ -217,6 +229,7 @@ aim_status aim_plan_info(const aim_plan *plan, aim_info *out) {
     out->fused_projection[i][0] = md.fuse_proj[0];
     out->fused_projection[i][1] = md.fuse_proj[1];
     out->planar_z[i] = md.planar_z;
+    for (int j = 0; j < AIM_NSETUP; ++j) out->setup_ms[i][j] = md.setup_ms[j];
   }
   out->device_bytes = plan->device_bytes;
   return AIM_OK;

@@ -57,7 +57,7 @@ void host_plan_build(const aim_mesh &m, const aim_params &p, HostPlan *hp) {
   if (!(m.freq_hz > 0)) fail_arg("freq_hz must be > 0");
   if (m.nv <= 0 || m.nt <= 0 || !m.verts || !m.tris) fail_arg("empty mesh");
   if (!(p.h_lambda > 0)) fail_arg("h_lambda must be > 0");
-  if (p.order < 1 || p.order > 4) fail_arg("order must be in 1..4");
+  if (p.order < 1 || p.order > 5) fail_arg("order must be in 1..5");
   if (!(p.near_radius_lambda >= 0)) fail_arg("near_radius_lambda must be >= 0");
   if (m.nv > INT32_MAX || m.nt > INT32_MAX) fail_arg("mesh too large");
 

@@ -323,6 +323,12 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
   const HostPlan &h = md.hp;
   const int M = h.order, K = h.K;
   const int64_t n = h.n;
+  double t_phase = wall_ms();
+  auto phase_done = [&](int which) {  // the stream is synchronised at each phase end
+    const double t = wall_ms();
+    md.setup_ms[which] = t - t_phase;
+    t_phase = t;
+  };
   // geometry and tables
   md.verts = upload(pl, h.verts.data(), h.verts.size(), s);
   md.tris = upload(pl, h.tris.data(), h.tris.size(), s);
@@ -447,6 +453,7 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
     HIPCHECK(hipStreamSynchronize(s));
     dev_free(pl, dsrc);
   }
+  phase_done(AIM_SETUP_PROJECTION);
 
   // FFT plans, twiddles, Green's spectrum octant
   for (int d = 0; d < 3; ++d) {
@@ -497,6 +504,7 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
     }
     HIPCHECK(hipStreamSynchronize(s));
   }
+  phase_done(AIM_SETUP_GREEN);
 
   // near zone: offsets table size from the largest anchor difference
   int D = 0;
@@ -528,6 +536,7 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
     LAUNCHCHECK();
   }
   HIPCHECK(hipStreamSynchronize(s));
+  phase_done(AIM_SETUP_NEAR_FILL);
   dev_free(pl, gtab);
   dev_free(pl, anchor3);
   md.area = area;  // kept for excitation and RCS

@@ -69,7 +69,7 @@ def test_host_plan_plate16_counts():
 
 def test_host_plan_other_orders():
     m = sphere_mesh(0.5, 0.3e9, nf=4)
-    for M in (1, 3):
+    for M in (1, 3, 4, 5):
         _compare_host_plan(m, h=0.08, M=M, rn=0.25)
 
 
@@ -94,7 +94,53 @@ def test_error_paths():
     with pytest.raises(lib_aim.AimError) as e:
         lib_aim.host_plan(m.verts, m.tris, m.freq_hz, order=0)
     assert e.value.status == lib_aim.AIM_ERR_ARG
+    with pytest.raises(lib_aim.AimError) as e:
+        lib_aim.host_plan(m.verts, m.tris, m.freq_hz, order=6)
+    assert e.value.status == lib_aim.AIM_ERR_ARG
     # a single triangle has no interior edge
     with pytest.raises(lib_aim.AimError) as e:
         lib_aim.host_plan(v[:3], np.array([[0, 1, 2]]), 0.3e9)
     assert e.value.status == lib_aim.AIM_ERR_MESH
+
+
+def test_binding_layouts_and_constants_match_header(tmp_path):
+    """The ctypes structures have the sizes and field offsets of the C
+    declarations, and every #define the binding mirrors has the same value."""
+    import ctypes
+    import shutil
+    import subprocess
+
+    cc = shutil.which("g++") or shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"aim_info": lib_aim.AimInfo, "aim_params": lib_aim.AimParams,
+               "aim_solve_opts": lib_aim.AimSolveOpts, "aim_solve_stats": lib_aim.AimSolveStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "aim.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-x", "c", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, fname, val = ln.split()
+        got[(cname, fname)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+    text = open(os.path.join(ROOT, "include", "aim.h")).read()
+    defines = dict(re.findall(r"#define\s+(AIM_[A-Z0-9_]+)\s+(-?\d+)\b", text))
+    for name, val in defines.items():
+        if hasattr(lib_aim, name):
+            assert getattr(lib_aim, name) == int(val), name
+    enums = dict(re.findall(r"\b(AIM_[A-Z0-9_]+)\s*=\s*(-?\d+)", text))
+    for name, val in enums.items():
+        if hasattr(lib_aim, name):
+            assert getattr(lib_aim, name) == int(val), name
+    assert lib_aim.SETUP_PHASES[lib_aim.AIM_NSETUP - 1] == "tune"

@@ -27,10 +27,17 @@ def _log(msg):
     sys.stdout.flush()
 
 
+# name -> (mesh, stencil order M); the higher orders reach the paper's
+# fifth-order reference setting (odd M puts a flat plate between grid
+# planes, even M on one)
 CASES = {
-    "plate1": lambda: plate_mesh(1.0, 0.3e9),
-    "sphere05": lambda: sphere_mesh(0.5, 0.3e9, nf=4),
-    "plate2j": lambda: plate_mesh(2.0, 0.3e9, jitter_seed=1001),
+    "plate1": (lambda: plate_mesh(1.0, 0.3e9), 2),
+    "sphere05": (lambda: sphere_mesh(0.5, 0.3e9, nf=4), 2),
+    "plate2j": (lambda: plate_mesh(2.0, 0.3e9, jitter_seed=1001), 2),
+    "sphere05_m3": (lambda: sphere_mesh(0.5, 0.3e9, nf=4), 3),
+    "plate2j_m4": (lambda: plate_mesh(2.0, 0.3e9, jitter_seed=1001), 4),
+    "plate1_m5": (lambda: plate_mesh(1.0, 0.3e9), 5),
+    "sphere05_m5": (lambda: sphere_mesh(0.5, 0.3e9, nf=4), 5),
 }
 
 
@@ -39,14 +46,15 @@ class Case:
         from paper_1010_1456_amd import aim as A
 
         self.name = name
-        self.mesh = CASES[name]()
+        make, self.order = CASES[name]
+        self.mesh = make()
         m = self.mesh
         self.k = wavenumber(m.freq_hz)
-        _log(f"[case {name}] oracle set-up")
+        _log(f"[case {name}] oracle set-up (M={self.order})")
         self.rwg = build_rwg(m.verts, m.tris)
-        self.op = oaim.build_operator(self.rwg, self.k, 0.1 * m.lam, 2, 0.3 * m.lam)
+        self.op = oaim.build_operator(self.rwg, self.k, 0.1 * m.lam, self.order, 0.3 * m.lam)
         _log(f"[case {name}] GPU set-up N={self.rwg.n}")
-        self.plan = A.Plan([(m.verts, m.tris, m.freq_hz)])
+        self.plan = A.Plan([(m.verts, m.tris, m.freq_hz)], order=self.order)
         torch.cuda.synchronize()
         info = self.plan.info()
         self.pad = info["pad"][0]
@@ -153,6 +161,39 @@ def test_matvec_mixed(name):
     for r in range(2):
         assert rel(y[r], ref32[r]) <= 2e-5
     assert rel(y, ref) <= 1e-4
+
+
+@pytest.mark.parametrize("name,plane", [("plate1", 1), ("plate2j_m4", 2), ("plate1_m5", -1),
+                                        ("sphere05", -1)])
+def test_planar_detection(name, plane):
+    """A flat plate takes the in-plane propagation when every projection
+    weight falls on one grid plane: even M puts it on the middle plane, odd M
+    between two planes (weights on all M + 1 planes)."""
+    c = case(name)
+    assert c.plan.info()["planar_z"][0] == plane
+    if plane >= 0:
+        nodes = oaim._node_index(c.op.grid, c.op.anc) % int(c.op.grid.n[2])
+        assert np.all(np.where(np.abs(c.op.lam).max(axis=1) > 0, nodes == plane, True))
+
+
+def test_setup_phase_times():
+    """Every set-up phase is timed; the near-zone fill and the host plan take
+    measurable time, and together the phases stay within the plan's wall time."""
+    import time
+
+    from paper_1010_1456_amd import aim as A
+
+    m = CASES["sphere05"][0]()
+    t0 = time.perf_counter()
+    plan = A.Plan([(m.verts, m.tris, m.freq_hz)])
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    t = plan.info()["setup_ms"][0]
+    assert tuple(t) == A.SETUP_PHASES
+    assert all(v >= 0 for v in t.values())
+    assert t["host_plan"] > 0 and t["near_fill"] > 0 and t["projection"] > 0
+    assert sum(t.values()) <= wall_ms
+    plan.close()
 
 
 def test_matvec_direct_sum_agrees():

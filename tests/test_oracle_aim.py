@@ -69,6 +69,33 @@ def test_moment_identity(which, plate, sphere):
         assert np.abs(lhs - rhs).max() <= 1e-12 * scale * h_pow
 
 
+@pytest.mark.parametrize("M", [1, 3, 4, 5])
+def test_moment_identity_other_orders(M):
+    """The same identity at every supported stencil order, on a sphere and
+    on a jittered plate (up to fifth order: the paper's reference setting)."""
+    for mesh in (sphere_mesh(0.4, F, nf=2), plate_mesh(1.0, F, jitter_seed=7)):
+        rwg = build_rwg(mesh.verts, mesh.tris)
+        grid = aim.grid_plan(rwg.verts, 0.1 * LAM, M)
+        anc = aim.anchors(grid, rwg.centre)
+        lam = aim.projection(rwg, grid, anc)
+        assert lam.shape == (rwg.n, 4, (M + 1) ** 3)
+        assert np.all(anc >= 0) and np.all(anc + M < np.asarray(grid.n))
+        nodes = _node_coords(grid, anc)
+        c = rwg.centre
+        scale = np.abs(lam).max()
+        for alpha in itertools.product(range(M + 1), repeat=3):
+            mono = np.prod((nodes - c[:, None, :]) ** np.asarray(alpha), axis=2)
+            lhs = np.einsum("nqu,nu->nq", lam, mono)
+            rhs = _quad_moments(rwg, c, alpha)
+            assert np.abs(lhs - rhs).max() <= 1e-11 * scale * grid.h ** sum(alpha)
+        # one order more is not matched in general (the identity is tight)
+        alpha = (M + 1, 0, 0)
+        mono = np.prod((nodes - c[:, None, :]) ** np.asarray(alpha), axis=2)
+        lhs = np.einsum("nqu,nu->nq", lam, mono)
+        rhs = _quad_moments(rwg, c, alpha)
+        assert np.abs(lhs - rhs).max() > 1e-6 * scale * grid.h ** (M + 1)
+
+
 def test_lagrange_equals_vandermonde_solve(sphere):
     """Lambda from Lagrange weights equals the solution of the (M+1)^3
     moment-matching system V^T Lambda = moments."""
