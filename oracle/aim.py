@@ -31,6 +31,16 @@ Product. y = Z^near x + j k eta [ sum_q Lambda_q^T (g * Lambda_q x)
   - k^-2 Lambda_d^T (g * Lambda_d x) ], where * is the discrete convolution
   over grid nodes: ``matvec_direct`` sums it directly over occupied nodes,
   ``matvec_fft`` evaluates it by zero-padded FFTs of any size P_d >= 2N_d - 1.
+Combined field (closed scatterers, Section 2.2: CFIE with alpha = 0.6; the
+  equations are in ``mfie``). The MFIE operator tests the curl of the vector
+  potential A_e = g * Lambda_e x (e = x, y, z), which the grid already holds,
+  with t_m = f_m x n: its interpolant's curl gives the curl weights
+      W[m, e, u] = sum_{T in T+-} A_T sum_p w_p (t_m(r_p) x grad l_u(r_p))_e,
+  exact (with the 7-point rule) for fields of tensor degree <= M. Then
+      Z^grid = alpha j k eta [ ... as above ... ] - (1 - alpha) eta W^T g Lambda,
+  Z^near = alpha Z^E,MOM + (1 - alpha) eta Z^H,MOM - Z^grid, and the product
+  interpolates alpha j k eta [ ... ] - (1 - alpha) eta sum_e W_e^T phi_e from
+  the same four propagated grids.
 
 FFT thread count follows ``scipy.fft.set_workers`` (default: one worker).
 """
@@ -47,6 +57,7 @@ from scipy.spatial import cKDTree
 
 from . import quadrature as quad
 from .constants import ETA0
+from .mfie import normals, sparse_zh
 from .mom import sparse_z
 from .rwg import RWG
 
@@ -103,6 +114,54 @@ def stencil_weights(grid: Grid, anchor: np.ndarray, pts: np.ndarray) -> np.ndarr
     lz = lagrange_1d(xi[..., 2], M)
     w = lx[..., :, None, None] * ly[..., None, :, None] * lz[..., None, None, :]
     return w.reshape(w.shape[:-3] + (grid.K,))
+
+
+def lagrange_1d_deriv(xi: np.ndarray, M: int) -> np.ndarray:
+    """d l_s / d xi for nodes 0..M at local coordinate xi: (..., M+1)."""
+    out = np.zeros(xi.shape + (M + 1,))
+    for s in range(M + 1):
+        for j in range(M + 1):  # product rule: drop factor j
+            if j == s:
+                continue
+            term = np.full(xi.shape, 1.0 / (s - j))
+            for r in range(M + 1):
+                if r != s and r != j:
+                    term = term * (xi - r) / (s - r)
+            out[..., s] += term
+    return out
+
+
+def stencil_gradients(grid: Grid, anchor: np.ndarray, pts: np.ndarray) -> np.ndarray:
+    """grad l_u at points pts (..., 3) for stencils at anchors (..., 3):
+    (..., K, 3) with u = (i (M+1) + j)(M+1) + k, in 1/metres."""
+    M = grid.order
+    xi = (pts - grid.x0) / grid.h - anchor
+    L = [lagrange_1d(xi[..., c], M) for c in range(3)]
+    D = [lagrange_1d_deriv(xi[..., c], M) / grid.h for c in range(3)]
+    gx = D[0][..., :, None, None] * L[1][..., None, :, None] * L[2][..., None, None, :]
+    gy = L[0][..., :, None, None] * D[1][..., None, :, None] * L[2][..., None, None, :]
+    gz = L[0][..., :, None, None] * L[1][..., None, :, None] * D[2][..., None, None, :]
+    g = np.stack([gx, gy, gz], axis=-1)
+    return g.reshape(g.shape[:-4] + (grid.K, 3))
+
+
+def curl_projection(rwg: RWG, grid: Grid, anc: np.ndarray) -> np.ndarray:
+    """W[n, e, u] = int over T+- of (t_n x grad l_u)_e dS with t_n = f_n x n_T,
+    by the 7-point rule: (N, 3, K) float64."""
+    N = rwg.n
+    W = np.zeros((N, 3, grid.K))
+    nrm = normals(rwg)
+    for side, free, sgn in ((rwg.tplus, rwg.vplus, 1.0), (rwg.tminus, rwg.vminus, -1.0)):
+        tri = rwg.verts[rwg.tris[side]]
+        pts = quad.points(tri)  # (N, 7, 3)
+        a = rwg.area[side]
+        F = sgn * (rwg.length / (2.0 * a))[:, None, None] * (pts - rwg.verts[free][:, None, :])
+        t = np.cross(F, nrm[side][:, None, :])  # (N, 7, 3)
+        gl = stencil_gradients(grid, anc[:, None, :], pts)  # (N, 7, K, 3)
+        c = np.cross(t[:, :, None, :], gl)  # (N, 7, K, 3)
+        aw = a[:, None] * quad.WEIGHTS[None, :]
+        W += np.einsum("np,npue->neu", aw, c)
+    return W
 
 
 def projection(rwg: RWG, grid: Grid, anc: np.ndarray) -> np.ndarray:
@@ -162,8 +221,10 @@ def near_pairs(centres: np.ndarray, r_near: float):
 
 
 def zgrid_entries(k: float, grid: Grid, lam: np.ndarray, anc: np.ndarray,
-                  rows: np.ndarray, cols: np.ndarray) -> np.ndarray:
-    """Z^grid_mn for pairs (rows[i], cols[i]), grouped by anchor offset."""
+                  rows: np.ndarray, cols: np.ndarray, curl: np.ndarray | None = None,
+                  alpha: float = 1.0) -> np.ndarray:
+    """Z^grid_mn for pairs (rows[i], cols[i]), grouped by anchor offset; with
+    curl weights, the combined-field form."""
     off = node_offsets(grid)
     out = np.zeros(rows.shape[0], dtype=np.complex128)
     delta = anc[rows] - anc[cols]
@@ -179,6 +240,9 @@ def zgrid_entries(k: float, grid: Grid, lam: np.ndarray, anc: np.ndarray,
         t = np.einsum("uv,pqv->pqu", Gb, Ln)  # (P, 4, K)
         s = np.einsum("pqu,pqu->pq", Lm, t)  # (P, 4)
         out[sel] = pref * (s[:, 0] + s[:, 1] + s[:, 2] - s[:, 3] / k**2)
+        if curl is not None:
+            kt = np.einsum("peu,peu->p", curl[rows[sel]], t[:, :3, :])
+            out[sel] = alpha * out[sel] - (1.0 - alpha) * ETA0 * kt
     return out
 
 
@@ -191,23 +255,34 @@ class AIMOperator:
     lam: np.ndarray  # (N, 4, K)
     near: scipy.sparse.csr_matrix  # Z^near
     zmom_diag: np.ndarray  # diag of Z^MOM (Jacobi preconditioner)
+    curl: np.ndarray | None = None  # (N, 3, K) curl weights (combined field only)
+    alpha: float = 1.0  # combined-field parameter (1: EFIE)
 
     @property
     def n(self) -> int:
         return self.rwg.n
 
 
-def build_operator(rwg: RWG, k: float, h: float, order: int, r_near: float) -> AIMOperator:
+def build_operator(rwg: RWG, k: float, h: float, order: int, r_near: float,
+                   cfie_alpha: float | None = None) -> AIMOperator:
+    """The AIM operator of the EFIE, or with ``cfie_alpha`` of the combined
+    field equation alpha EFIE + (1 - alpha) eta MFIE (closed meshes)."""
     grid = grid_plan(rwg.verts, h, order)
     anc = anchors(grid, rwg.centre)
     lam = projection(rwg, grid, anc)
     indptr, indices = near_pairs(rwg.centre, r_near)
     rows = np.repeat(np.arange(rwg.n), np.diff(indptr))
     zmom = sparse_z(rwg, k, indptr, indices)
-    zgrid = zgrid_entries(k, grid, lam, anc, rows, indices)
+    curl, alpha = None, 1.0
+    if cfie_alpha is not None:
+        alpha = float(cfie_alpha)
+        curl = curl_projection(rwg, grid, anc)
+        zmom = alpha * zmom + (1.0 - alpha) * ETA0 * sparse_zh(rwg, k, indptr, indices)
+    zgrid = zgrid_entries(k, grid, lam, anc, rows, indices, curl, alpha)
     near = scipy.sparse.csr_matrix((zmom - zgrid, indices, indptr), shape=(rwg.n, rwg.n))
     diag = zmom[rows == indices]
-    return AIMOperator(rwg=rwg, k=k, grid=grid, anc=anc, lam=lam, near=near, zmom_diag=diag)
+    return AIMOperator(rwg=rwg, k=k, grid=grid, anc=anc, lam=lam, near=near, zmom_diag=diag,
+                       curl=curl, alpha=alpha)
 
 
 def _node_index(grid: Grid, anc: np.ndarray) -> np.ndarray:
@@ -229,7 +304,8 @@ def anterpolate(op: AIMOperator, x: np.ndarray) -> np.ndarray:
 
 
 def interpolate(op: AIMOperator, phi: np.ndarray) -> np.ndarray:
-    """Interpolation step: y^far = j k eta [sum_q Lambda_q^T phi_q - k^-2 Lambda_d^T phi_d]."""
+    """Interpolation step: y^far = j k eta [sum_q Lambda_q^T phi_q - k^-2 Lambda_d^T phi_d]
+    (combined field: alpha times that, minus (1 - alpha) eta sum_e W_e^T phi_e)."""
     idx = _node_index(op.grid, op.anc)
     k = op.k
     out = np.zeros((phi.shape[0], op.n), dtype=np.complex128)
@@ -239,6 +315,11 @@ def interpolate(op: AIMOperator, phi: np.ndarray) -> np.ndarray:
             acc += np.sum(op.lam[:, q, :] * phi[r, q][idx], axis=1)
         acc -= np.sum(op.lam[:, 3, :] * phi[r, 3][idx], axis=1) / k**2
         out[r] = 1j * k * ETA0 * acc
+        if op.curl is not None:
+            kt = np.zeros(op.n, dtype=np.complex128)
+            for e in range(3):
+                kt += np.sum(op.curl[:, e, :] * phi[r, e][idx], axis=1)
+            out[r] = op.alpha * out[r] - (1.0 - op.alpha) * ETA0 * kt
     return out
 
 

@@ -73,3 +73,43 @@ def triangle_potentials(tri: np.ndarray, r: np.ndarray):
         Ip += 0.5 * np.outer(R0sq * f + lp * Rp - lm * Rm, uhat)
     Iv = Ip - (d * I1)[:, None] * n
     return I1, Iv
+
+
+def triangle_gradient(tri: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """G1(r) = integral over T' of grad_r 1/|r - r'| dS', (P, 3), in closed form.
+
+    The in-plane part follows from the divergence theorem on T' (the gradient
+    moves onto r' with a sign change and becomes a boundary integral of 1/R
+    along each edge, which is the edge's log term f_i); the normal part is the
+    d-derivative of I1, -sign(d) times the solid angle Omega that T' subtends
+    at r (Omega is the bracketed arctan sum of I1):
+
+        G1 = - sum_i u_i f_i - n sign(d) Omega.
+
+    At d = 0 the normal part is taken as zero (its principal value)."""
+    tri = np.asarray(tri, dtype=np.float64)
+    r = np.atleast_2d(np.asarray(r, dtype=np.float64))
+    v0, v1, v2 = tri
+    n = np.cross(v1 - v0, v2 - v0)
+    n = n / np.linalg.norm(n)
+    d = (r - v0) @ n
+    rho = r - d[:, None] * n
+    ad = np.abs(d)
+    omega = np.zeros(r.shape[0])
+    g = np.zeros((r.shape[0], 3))
+    for a, b in ((v0, v1), (v1, v2), (v2, v0)):
+        lhat = (b - a) / np.linalg.norm(b - a)
+        uhat = np.cross(lhat, n)
+        t0 = (a - rho) @ uhat
+        lp = (b - rho) @ lhat
+        lm = (a - rho) @ lhat
+        R0sq = t0 * t0 + d * d
+        Rp = np.sqrt(lp * lp + R0sq)
+        Rm = np.sqrt(lm * lm + R0sq)
+        f = _log_ratio(Rp, lp, Rm, lm, R0sq)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            atp = np.where(R0sq > 0.0, np.arctan2(t0 * lp, R0sq + ad * Rp), 0.0)
+            atm = np.where(R0sq > 0.0, np.arctan2(t0 * lm, R0sq + ad * Rm), 0.0)
+        omega += atp - atm
+        g -= np.outer(f, uhat)
+    return g - np.outer(np.sign(d) * omega, n)
