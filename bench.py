@@ -145,6 +145,7 @@ def stage_bytes(info, mesh, nrhs, s_grid, s_real, s_x, s_y, path):
     F = 4 * nrhs
     H = (Px // 2 + 1) * (Py // 2 + 1) * (Pz // 2 + 1)
     lam = n * (4 * K * s_real + 4)
+    curl = 3 * n * K * s_real if info.get("cfie_alpha") is not None else 0.0  # combined field
     if info["planar_z"][mesh] >= 0:  # scatterer in one grid plane: everything on that plane
         A1, A2 = Nx * Ny, Nx * Py
         H2 = (Px // 2 + 1) * (Py // 2 + 1)
@@ -170,7 +171,7 @@ def stage_bytes(info, mesh, nrhs, s_grid, s_real, s_x, s_y, path):
         F * (V2 + V1) * s_grid,                                        # inverse y
         F * (V1 + V0) * s_grid,                                        # inverse z
         F * V0 * s_grid + lam + nnz * (s_grid + 4) + 4 * (n + 1)
-        + nrhs * n * (s_x + s_y),                                      # interp + near
+        + nrhs * n * (s_x + s_y) + curl,                               # interp + near
     ], dtype=np.float64)
 
 
@@ -224,7 +225,7 @@ def time_path(plan, A, prec, x, y, steps, warmup):
     return wall, stage_ms / steps, total_ms
 
 
-def cpu_baseline(mesh, cfg, nrhs, pad):
+def cpu_baseline(mesh, cfg, nrhs, pad, cfie_alpha=None):
     """The FP64 oracle's FFT-form product on the host cores (one product)."""
     import scipy.fft
     import scipy.sparse
@@ -246,6 +247,9 @@ def cpu_baseline(mesh, cfg, nrhs, pad):
                                    shape=(rwg.n, rwg.n))
     op = oaim.AIMOperator(rwg=rwg, k=k, grid=grid, anc=anc, lam=lam, near=near,
                           zmom_diag=np.ones(rwg.n, dtype=np.complex128))
+    if cfie_alpha is not None:
+        op.curl = oaim.curl_projection(rwg, grid, anc)
+        op.alpha = cfie_alpha
     with scipy.fft.set_workers(cores):
         ghat = oaim.green_spectrum(k, grid, pad)
         log(f"[cpu_baseline] oracle set-up {time.perf_counter() - t_setup:.1f} s")
@@ -395,6 +399,9 @@ def main(argv=None):
                     help="right-hand sides per scatterer (default 1; 16 for batch6)")
     ap.add_argument("--order", type=int, default=None,
                     help="stencil order M (default: the workload's, 2)")
+    ap.add_argument("--cfie", type=float, default=None, metavar="ALPHA",
+                    help="solve the combined-field equation alpha EFIE + (1 - alpha) eta MFIE "
+                         "(closed scatterers; the paper's alpha is 0.6) instead of the EFIE")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--solve-iters", type=int, default=300,
                     help="GMRES iteration budget of the solve comparison (0 skips it)")
@@ -442,7 +449,8 @@ def main(argv=None):
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     plan = A.Plan([(m.verts, m.tris, m.freq_hz) for m in meshes], h_lambda=cfg["h_lambda"],
-                  order=cfg["order"], near_radius_lambda=cfg["near_radius_lambda"])
+                  order=cfg["order"], near_radius_lambda=cfg["near_radius_lambda"],
+                  cfie_alpha=args.cfie)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = plan.info()
@@ -491,7 +499,7 @@ def main(argv=None):
                 "plate128": "PEC plate 128 lambda at 38.4 GHz, 1152x1152 squares",
                 "batch6": "6 scatterers in one plan at 0.3 GHz: PEC plates 2, 4, 8 lambda and spheres "
                           "1, 2, 4 lambda (seeded vertex jitter), R right-hand sides each",
-            }[args.workload] + f"; EFIE-AIM h={cfg['h_lambda']} lambda, M={cfg['order']} ({(cfg['order'] + 1) ** 3}-node "
+            }[args.workload] + f"; {'EFIE' if args.cfie is None else f'CFIE (alpha {args.cfie})'}-AIM h={cfg['h_lambda']} lambda, M={cfg['order']} ({(cfg['order'] + 1) ** 3}-node "
                                f"stencils), near radius {cfg['near_radius_lambda']} lambda; "
                                f"N={n}, grid {info['grid'] if info['nmesh'] > 1 else info['grid'][0]}, "
                                f"FFT {info['pad'] if info['nmesh'] > 1 else info['pad'][0]}, "
@@ -536,7 +544,7 @@ def main(argv=None):
         out["solve"] = solve_compare(plan, A, mesh, args.workload, args.solve_iters)
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(mesh, cfg, R, tuple(info["pad"][0]))
+        out["cpu_baseline"] = cpu_baseline(mesh, cfg, R, tuple(info["pad"][0]), args.cfie)
         out["fill"]["cpu_oracle"] = cpu_fill_baseline(cfg, mesh.freq_hz)
     print(json.dumps(out), flush=True)
     plan.close()

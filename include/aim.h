@@ -82,7 +82,11 @@ typedef struct {
  *                     distance (wavelengths, >= 0), e.g. 0.3 (= 3 h)
  * fft_min_pad         0: FFT length per dimension = smallest supported
  *                     length >= 2 N_d - 1; otherwise a lower bound on it
- * flags               AIM_FLAG_* below */
+ * flags               AIM_FLAG_* below
+ * cfie_alpha          with AIM_FLAG_CFIE: the combination parameter alpha in
+ *                     [0, 1] of alpha EFIE + (1 - alpha) eta MFIE (the paper
+ *                     uses 0.6 for its closed scatterers, Section 2.2);
+ *                     ignored otherwise */
 typedef struct {
   double h_lambda;
   int32_t order;
@@ -90,9 +94,19 @@ typedef struct {
   double near_radius_lambda;
   int32_t flags;
   int32_t reserved;
+  double cfie_alpha;
 } aim_params;
 
 #define AIM_FLAG_NO_MIXED 1 /* keep only FP64 operator data (AIM_MIXED -> AIM_ERR_STATE) */
+/* Combined-field equation instead of the EFIE (Section 2.2): Galerkin-tested
+ * alpha EFIE + (1 - alpha) eta MFIE, with MFIE J/2 - n x PV int grad G x J dS'
+ * = n x H_inc and n the outward normal, (v1 - v0) x (v2 - v0) of each
+ * triangle. Every mesh must be closed (every edge shared by two triangles)
+ * and consistently oriented with positive enclosed volume, else AIM_ERR_MESH;
+ * alpha outside [0, 1] gives AIM_ERR_ARG. The product, the solve (its
+ * right-hand side V = alpha <f, E_inc> + (1 - alpha) <f, n x (k_hat x E_inc)>)
+ * and the Jacobi preconditioner then use the combined operator. */
+#define AIM_FLAG_CFIE 2
 
 /* Device memory provider. alloc returns device memory of >= bytes (NULL on
  * failure), ordered on `stream`; free releases it. Passing NULL for the
@@ -157,6 +171,7 @@ typedef struct {
                                                near-zone fill (FP64 quadrature of Z^MOM - Z^grid),
                                                variant tuning (paper Section 2.4, Fig. 4, times
                                                the matrix fill) */
+  double cfie_alpha;                    /* combined-field parameter, or -1 for the EFIE */
 } aim_info;
 
 /* GMRES options. restart m (<= 200), relative-residual tolerance on
@@ -285,11 +300,15 @@ void aim_host_plan_destroy(aim_host_plan *hp);
  *  AIM_DATA_ZDIAG64   [n] c128                diag of Z^MOM
  *  AIM_DATA_GHAT64    [Hx][Hy][Hz] c128       Green's spectrum octant,
  *                     H_d = P_d/2 + 1, scaled by 1/(P_x P_y P_z)
+ *  AIM_DATA_CURL64    [n][3][(M+1)^3] double  curl weights of the combined
+ *                     field (AIM_FLAG_CFIE plans only): int (t_n x grad l_u)_e
+ *                     with t_n = f_n x n
  * `bytes` must equal the size of the item. */
 #define AIM_DATA_LAMBDA64 1
 #define AIM_DATA_NEAR64 2
 #define AIM_DATA_ZDIAG64 3
 #define AIM_DATA_GHAT64 4
+#define AIM_DATA_CURL64 5
 aim_status aim_export(const aim_plan *plan, int32_t mesh, int32_t what, void *host_dst,
                       size_t bytes);
 

@@ -29,12 +29,14 @@ AIM_MIXED = 1
 AIM_MIXED_IO64 = 2
 AIM_NSTAGE = 7
 AIM_FLAG_NO_MIXED = 1
+AIM_FLAG_CFIE = 2
 AIM_SOLVE_NO_GRAPH = 1
 AIM_MAX_MESH = 16
 AIM_DATA_LAMBDA64 = 1
 AIM_DATA_NEAR64 = 2
 AIM_DATA_ZDIAG64 = 3
 AIM_DATA_GHAT64 = 4
+AIM_DATA_CURL64 = 5
 AIM_NSETUP = 5
 # set-up phases of aim_info.setup_ms, in order
 SETUP_PHASES = ("host_plan", "projection", "green", "near_fill", "tune")
@@ -59,7 +61,8 @@ class AimMesh(ctypes.Structure):
 
 class AimParams(ctypes.Structure):
     _fields_ = [("h_lambda", c_double), ("order", c_int32), ("fft_min_pad", c_int32),
-                ("near_radius_lambda", c_double), ("flags", c_int32), ("reserved", c_int32)]
+                ("near_radius_lambda", c_double), ("flags", c_int32), ("reserved", c_int32),
+                ("cfie_alpha", c_double)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_void_p, c_size_t, c_void_p)
@@ -82,7 +85,8 @@ class AimInfo(ctypes.Structure):
                 ("h", c_double * M), ("x0", (c_double * 3) * M), ("k", c_double * M),
                 ("bytes_fp64", c_double * M), ("bytes_mixed", c_double * M),
                 ("fused_projection", (c_int32 * 2) * M), ("planar_z", c_int32 * M),
-                ("device_bytes", c_double), ("setup_ms", (c_double * AIM_NSETUP) * M)]
+                ("device_bytes", c_double), ("setup_ms", (c_double * AIM_NSETUP) * M),
+                ("cfie_alpha", c_double)]
 
 
 class AimSolveOpts(ctypes.Structure):
@@ -153,9 +157,11 @@ def _mesh_struct(verts, tris, freq_hz, keep):
                    t.ctypes.data_as(POINTER(c_int32)), float(freq_hz))
 
 
-def _params(h_lambda, order, near_radius_lambda, fft_min_pad=0, flags=0):
+def _params(h_lambda, order, near_radius_lambda, fft_min_pad=0, flags=0, cfie_alpha=None):
+    if cfie_alpha is not None:
+        flags |= AIM_FLAG_CFIE
     return AimParams(float(h_lambda), int(order), int(fft_min_pad), float(near_radius_lambda),
-                     int(flags), 0)
+                     int(flags), 0, float(cfie_alpha) if cfie_alpha is not None else 0.0)
 
 
 def _waves(waves):
@@ -165,12 +171,13 @@ def _waves(waves):
     return arr
 
 
-def host_plan(verts, tris, freq_hz, h_lambda=0.1, order=2, near_radius_lambda=0.3, fft_min_pad=0):
+def host_plan(verts, tris, freq_hz, h_lambda=0.1, order=2, near_radius_lambda=0.3, fft_min_pad=0,
+              cfie_alpha=None):
     """Host phase only (no GPU): RWG table, anchors, near-zone CSR, grid."""
     L = lib()
     keep = []
     m = _mesh_struct(verts, tris, freq_hz, keep)
-    p = _params(h_lambda, order, near_radius_lambda, fft_min_pad)
+    p = _params(h_lambda, order, near_radius_lambda, fft_min_pad, cfie_alpha=cfie_alpha)
     hp = c_void_p()
     _check(L.aim_host_plan_build(ctypes.byref(m), ctypes.byref(p), ctypes.byref(hp)))
     try:
@@ -226,7 +233,7 @@ class Plan:
     meshes: list of (verts (nv,3) metres, tris (nt,3), freq_hz)."""
 
     def __init__(self, meshes, h_lambda=0.1, order=2, near_radius_lambda=0.3, fft_min_pad=0,
-                 mixed=True, stream=None):
+                 mixed=True, stream=None, cfie_alpha=None):
         import torch
 
         self._torch = torch
@@ -239,7 +246,8 @@ class Plan:
         arr = (AimMesh * len(meshes))()
         for i, (v, t, f) in enumerate(meshes):
             arr[i] = _mesh_struct(v, t, f, keep)
-        p = _params(h_lambda, order, near_radius_lambda, fft_min_pad, 0 if mixed else AIM_FLAG_NO_MIXED)
+        p = _params(h_lambda, order, near_radius_lambda, fft_min_pad, 0 if mixed else AIM_FLAG_NO_MIXED,
+                    cfie_alpha)
         self._alloc = TorchAllocator(self.device)
         h = c_void_p()
         _check(L.aim_setup(arr, len(meshes), ctypes.byref(p), ctypes.byref(self._alloc.struct),
@@ -277,7 +285,8 @@ class Plan:
                               for i in range(nm)],
             planar_z=[inf.planar_z[i] for i in range(nm)],
             device_bytes=inf.device_bytes,
-            setup_ms=[dict(zip(SETUP_PHASES, inf.setup_ms[i])) for i in range(nm)])
+            setup_ms=[dict(zip(SETUP_PHASES, inf.setup_ms[i])) for i in range(nm)],
+            cfie_alpha=None if inf.cfie_alpha < 0 else inf.cfie_alpha)
 
     def _stream(self, stream):
         s = stream if stream is not None else self._torch.cuda.current_stream()
@@ -363,6 +372,8 @@ class Plan:
             out = np.zeros(n, dtype=np.complex128)
         elif what == AIM_DATA_GHAT64:
             out = np.zeros(tuple(p // 2 + 1 for p in pad), dtype=np.complex128)
+        elif what == AIM_DATA_CURL64:
+            out = np.zeros((n, 3, K), dtype=np.float64)
         else:
             raise ValueError(what)
         _check(lib().aim_export(self._h, mesh, what, c_void_p(out.ctypes.data), out.nbytes))

@@ -152,6 +152,11 @@ struct MeshDev {
   int plane_K = 0;                    // (M+1)^2
   int plane_npw = 16;                 // plane nodes per wave of the gather
   double setup_ms[AIM_NSETUP] = {0, 0, 0, 0, 0};  // wall time per set-up phase
+  // combined field only: curl weights W[n][e][u] = int (t_n x grad l_u)_e,
+  // t_n = f_n x n (the MFIE part is interpolated from the vector potential's
+  // grids with them)
+  double *curl64 = nullptr;  // n*3*K
+  float *curl32 = nullptr;
 };
 
 // milliseconds since an arbitrary epoch (steady clock)
@@ -169,6 +174,8 @@ struct Plan {
   hipStream_t setup_stream = nullptr;
   aim_params params{};
   bool mixed = true;
+  bool cfie = false;    // combined-field equation (alpha EFIE + (1 - alpha) eta MFIE)
+  double alpha = 1.0;   // its parameter
   int nmesh = 0;
   int64_t n_total = 0;
   std::vector<MeshDev> mesh;

@@ -105,7 +105,8 @@ static double model_bytes(const MeshDev &md, int sc, int sr) {
   }
   const double v0_terms = md.fuse_proj[sc == 16 ? 0 : 1] ? 2.0 : 4.0;
   const double grid = 4.0 * sc * (v0_terms * V0 + 4.0 * V1 + 4.0 * V2);
-  return vec + lam + nearb + ghat + grid;
+  const double curl = md.curl64 ? 3.0 * n * K * sr : 0.0;  // combined field: interpolation only
+  return vec + lam + curl + nearb + ghat + grid;
 }
 
 }  // namespace aim
@@ -175,6 +176,8 @@ aim_status aim_setup(const aim_mesh *meshes, int32_t nmesh, const aim_params *p,
   pl->setup_stream = (hipStream_t)hip_stream;
   pl->params = *p;
   pl->mixed = !(p->flags & AIM_FLAG_NO_MIXED);
+  pl->cfie = (p->flags & AIM_FLAG_CFIE) != 0;
+  pl->alpha = pl->cfie ? p->cfie_alpha : 1.0;
   pl->nmesh = nmesh;
   pl->mesh.resize(nmesh);
   aim_status st = guarded([&] {
@@ -229,6 +232,7 @@ aim_status aim_plan_info(const aim_plan *plan, aim_info *out) {
     out->fused_projection[i][0] = md.fuse_proj[0];
     out->fused_projection[i][1] = md.fuse_proj[1];
     out->planar_z[i] = md.planar_z;
+    out->cfie_alpha = plan->cfie ? plan->alpha : -1.0;
     for (int j = 0; j < AIM_NSETUP; ++j) out->setup_ms[i][j] = md.setup_ms[j];
   }
   out->device_bytes = plan->device_bytes;
@@ -389,6 +393,11 @@ aim_status aim_export(const aim_plan *plan, int32_t mesh, int32_t what, void *ho
     case AIM_DATA_GHAT64:
       src = md.ghat64;
       need = sizeof(double2) * md.H[0] * md.H[1] * md.H[2];
+      break;
+    case AIM_DATA_CURL64:
+      if (!md.curl64) return fail(AIM_ERR_STATE, "the plan has no curl weights (not a CFIE plan)");
+      src = md.curl64;
+      need = sizeof(double) * md.hp.n * 3 * md.hp.K;
       break;
     default:
       return fail(AIM_ERR_ARG, "unknown export item");

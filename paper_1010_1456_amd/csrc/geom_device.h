@@ -92,9 +92,137 @@ __host__ __device__ inline void triangle_potentials(const D3 *T, D3 r, double &I
   Iv = accv - (d * acc1) * n;
 }
 
+// G1 = int_T grad_r 1/|r - r'| dS' and Iv (as above) for a planar triangle.
+// In-plane part of G1 by the divergence theorem (minus the edge integrals of
+// 1/R along the outward edge normals: - sum_i u_i f_i); normal part the
+// d-derivative of I1, -sign(d) times the solid angle of T seen from r (the
+// arctan sum), zero in the plane of T.
+__host__ __device__ inline void triangle_gradient(const D3 *T, D3 r, D3 &G1, D3 &Iv) {
+  D3 n = cross(T[1] - T[0], T[2] - T[0]);
+  n = (1.0 / norm(n)) * n;
+  const double d = dot(r - T[0], n);
+  const double ad = fabs(d);
+  const D3 rho = r - d * n;
+  double acc1 = 0.0, omega = 0.0;
+  D3 accv = d3(0, 0, 0), accg = d3(0, 0, 0);
+  for (int e = 0; e < 3; ++e) {
+    const D3 a = T[e], b = T[(e + 1) % 3];
+    D3 lhat = b - a;
+    lhat = (1.0 / norm(lhat)) * lhat;
+    const D3 uhat = cross(lhat, n);
+    const double t0 = dot(a - rho, uhat);
+    const double lp = dot(b - rho, lhat);
+    const double lm = dot(a - rho, lhat);
+    const double R0sq = t0 * t0 + d * d;
+    const double Rp = sqrt(lp * lp + R0sq);
+    const double Rm = sqrt(lm * lm + R0sq);
+    double f = 0.0, atp = 0.0, atm = 0.0;
+    if (R0sq > 0.0) {
+      f = log(r_plus_l(Rp, lp, R0sq)) - log(r_plus_l(Rm, lm, R0sq));
+      atp = atan2(t0 * lp, R0sq + ad * Rp);
+      atm = atan2(t0 * lm, R0sq + ad * Rm);
+    }
+    acc1 += t0 * f - ad * (atp - atm);
+    omega += atp - atm;
+    accv = accv + (0.5 * (R0sq * f + lp * Rp - lm * Rm)) * uhat;
+    accg = accg - f * uhat;
+  }
+  const double sg = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
+  G1 = accg - (sg * omega) * n;
+  Iv = accv - (d * acc1) * n;
+}
+
 struct C2 {
   double re, im;
 };
+
+// true if every vertex of Tn lies in the plane of Tm (relative tolerance
+// 1e-12 of the longer first edge): then the MFIE pair term vanishes
+__host__ __device__ inline bool coplanar(const D3 *Tm, const D3 *Tn) {
+  D3 n = cross(Tm[1] - Tm[0], Tm[2] - Tm[0]);
+  n = (1.0 / norm(n)) * n;
+  const double sc = fmax(norm(Tm[1] - Tm[0]), norm(Tn[1] - Tn[0]));
+  for (int v = 0; v < 3; ++v)
+    if (fabs(dot(Tn[v] - Tm[0], n)) > 1e-12 * sc) return false;
+  return true;
+}
+
+// K pair factor of the MFIE for test triangle Tm (free vertex pm, outward
+// normal nm) and a non-coplanar source triangle Tn (free vertex pn):
+//   int_Tm [(r - pm) x nm] . [J(r) x (r - pn)] dS,  J(r) = int_Tn grad_r G dS'
+// (grad G is parallel to r - r', so the source factor r' - pn becomes r - pn).
+// The RWG pair contribution is s_m s_n l_m l_n / (4 A_m A_n) times this.
+// `touch`: the first two terms of grad G in powers of R are integrated in
+// closed form, -(r - r')/(4 pi R^3) (G1) and -k^2 (r - r')/(8 pi R) (Iv), and
+// the smooth remainder (d/R) k^2/(4 pi) phi(kR) by the 7-point rule, with
+// phi(x) = (1 - (1 + j x) exp(-j x))/x^2 + 1/2 (series below x = 1e-2).
+__host__ __device__ inline C2 mfie_pair(const D3 *Tm, double Am, D3 pm, D3 nm, const D3 *Tn,
+                                        double An, D3 pn, double k, bool touch) {
+  const double inv4pi = 0.25 / 3.14159265358979323846;
+  double sre = 0.0, sim = 0.0;
+  for (int p = 0; p < 7; ++p) {
+    double wp;
+    const D3 rp = quad_point(Tm, p, &wp);
+    D3 jr = d3(0, 0, 0), ji = d3(0, 0, 0);
+    if (touch) {
+      D3 G1, Iv;
+      triangle_gradient(Tn, rp, G1, Iv);
+      jr = inv4pi * G1 + (0.5 * k * k * inv4pi) * Iv;
+    }
+    for (int q = 0; q < 7; ++q) {
+      double wq;
+      const D3 rq = quad_point(Tn, q, &wq);
+      const D3 dv = rp - rq;
+      const double R = norm(dv);
+      if (R == 0.0) continue;
+      double gr, gi;  // radial factor: grad = (gr + j gi) dv
+      if (!touch) {
+        // grad G = -(1 + j k R) exp(-j k R) / (4 pi R^3) dv
+        double sn, cs;
+        sincos(k * R, &sn, &cs);
+        const double c = -inv4pi / (R * R * R);
+        gr = c * (cs + k * R * sn);
+        gi = c * (k * R * cs - sn);
+      } else {
+        const double x = k * R;
+        double pr, pi;
+        if (x < 1e-2) {
+          const double x2 = x * x;
+          pr = x2 / 8.0 - x2 * x2 / 144.0;
+          pi = x / 3.0 - x2 * x / 30.0;
+        } else {
+          double sn, cs;
+          sincos(x, &sn, &cs);
+          // (1 + j x)(cos x - j sin x) = (cos x + x sin x) + j (x cos x - sin x)
+          pr = (1.0 - (cs + x * sn)) / (x * x) + 0.5;
+          pi = -(x * cs - sn) / (x * x);
+        }
+        const double c = k * k * inv4pi / R;
+        gr = c * pr;
+        gi = c * pi;
+      }
+      const double a = An * wq;
+      jr = jr + (a * gr) * dv;
+      ji = ji + (a * gi) * dv;
+    }
+    // [(r - pm) x nm] . [J x (r - pn)] = J . [(r - pn) x ((r - pm) x nm)]
+    const D3 cvec = cross(rp - pn, cross(rp - pm, nm));
+    sre += wp * dot(jr, cvec);
+    sim += wp * dot(ji, cvec);
+  }
+  return C2{sre * Am, sim * Am};
+}
+
+// int_T (r - pm) . (r - pn) dS by the 7-point rule (exact: quadratic)
+__host__ __device__ inline double gram_pair(const D3 *T, double A, D3 pm, D3 pn) {
+  double s = 0.0;
+  for (int p = 0; p < 7; ++p) {
+    double wp;
+    const D3 rp = quad_point(T, p, &wp);
+    s += wp * dot(rp - pm, rp - pn);
+  }
+  return s * A;
+}
 
 // Integral over test triangle Tm (free vertex pm) and source triangle Tn (free
 // vertex pn) of [(r - pm).(r' - pn) - 4/k^2] G(|r - r'|), i.e. the factor I of

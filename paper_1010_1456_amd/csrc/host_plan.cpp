@@ -59,6 +59,8 @@ void host_plan_build(const aim_mesh &m, const aim_params &p, HostPlan *hp) {
   if (!(p.h_lambda > 0)) fail_arg("h_lambda must be > 0");
   if (p.order < 1 || p.order > 5) fail_arg("order must be in 1..5");
   if (!(p.near_radius_lambda >= 0)) fail_arg("near_radius_lambda must be >= 0");
+  const bool cfie = (p.flags & AIM_FLAG_CFIE) != 0;
+  if (cfie && !(p.cfie_alpha >= 0.0 && p.cfie_alpha <= 1.0)) fail_arg("cfie_alpha must be in [0, 1]");
   if (m.nv > INT32_MAX || m.nt > INT32_MAX) fail_arg("mesh too large");
 
   HostPlan &h = *hp;
@@ -93,25 +95,28 @@ void host_plan_build(const aim_mesh &m, const aim_params &p, HostPlan *hp) {
     if (!(h.area[t] > min_area)) fail_mesh("degenerate triangle " + std::to_string(t));
   }
 
-  // edges: (lo, hi, triangle, local vertex opposite the edge), sorted
+  // edges: (lo, hi, triangle, local vertex opposite the edge, 1 if the
+  // triangle runs the edge from lo to hi), sorted
   struct E {
-    int32_t lo, hi, t, i;
+    int32_t lo, hi, t, i, fwd;
   };
   std::vector<E> e(3 * nt);
   for (int64_t t = 0; t < nt; ++t)
     for (int i = 0; i < 3; ++i) {
       int a = h.tris[3 * t + (i + 1) % 3], b = h.tris[3 * t + (i + 2) % 3];
-      e[3 * t + i] = {std::min(a, b), std::max(a, b), (int32_t)t, i};
+      e[3 * t + i] = {std::min(a, b), std::max(a, b), (int32_t)t, i, a < b ? 1 : 0};
     }
   std::sort(e.begin(), e.end(), [](const E &x, const E &y) {
     if (x.lo != y.lo) return x.lo < y.lo;
     if (x.hi != y.hi) return x.hi < y.hi;
     return x.t < y.t;
   });
+  bool closed = true;  // every edge shared by two triangles that run it in opposite directions
   for (size_t s = 0; s < e.size();) {
     size_t q = s + 1;
     while (q < e.size() && e[q].lo == e[s].lo && e[q].hi == e[s].hi) ++q;
     if (q - s > 2) fail_mesh("edge shared by more than two triangles");
+    if (q - s != 2 || e[s].fwd == e[s + 1].fwd) closed = false;
     if (q - s == 2) {
       h.e_lo.push_back(e[s].lo);
       h.e_hi.push_back(e[s].hi);
@@ -124,6 +129,19 @@ void host_plan_build(const aim_mesh &m, const aim_params &p, HostPlan *hp) {
   }
   const int64_t n = (int64_t)h.e_lo.size();
   if (n == 0) fail_mesh("mesh has no interior edge");
+  if (cfie) {
+    // enclosed volume sum v0 . (v1 x v2) / 6 > 0 for outward normals
+    double vol = 0.0;
+    for (int64_t t = 0; t < nt; ++t) {
+      const double *A = &h.verts[3 * (int64_t)h.tris[3 * t]], *B = &h.verts[3 * (int64_t)h.tris[3 * t + 1]],
+                   *C = &h.verts[3 * (int64_t)h.tris[3 * t + 2]];
+      vol += A[0] * (B[1] * C[2] - B[2] * C[1]) + A[1] * (B[2] * C[0] - B[0] * C[2]) +
+             A[2] * (B[0] * C[1] - B[1] * C[0]);
+    }
+    if (!closed || !(vol > 0.0))
+      fail_mesh("the combined-field equation needs a closed, consistently oriented mesh with "
+                "outward normals");
+  }
   h.n = n;
   h.len.resize(n);
   h.centre.resize(3 * n);

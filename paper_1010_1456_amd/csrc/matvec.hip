@@ -142,14 +142,18 @@ __device__ __forceinline__ V half_wave_sum(V v) {
 constexpr int kNearUnroll = 4;
 
 // RB right-hand sides per grid row (blockIdx.y): the stencil weights, the
-// near-zone entries and their columns are loaded once for the RB products
-template <typename T, typename TX, typename TY, int RB>
+// near-zone entries and their columns are loaded once for the RB products.
+// CF (combined field): y^far = keta j [sum_q Lambda_q^T phi_q - inv_k2
+// Lambda_d^T phi_d] - eta_h sum_e W_e^T phi_e, with keta = alpha k eta and
+// eta_h = (1 - alpha) eta; the curl weights W test the vector potential's curl.
+template <typename T, typename TX, typename TY, int RB, bool CF>
 __global__ void __launch_bounds__(256)
     k_interp_near(const cx<T> *__restrict__ phi, int64_t V0, int nrhs, const T *__restrict__ lam,
-                  const int32_t *__restrict__ anchor_lin, const int32_t *__restrict__ soff, int K,
-                  const int32_t *__restrict__ rowptr, const int32_t *__restrict__ cols,
-                  const cx<T> *__restrict__ nearv, const cx<TX> *__restrict__ x, int64_t ldx,
-                  cx<TY> *__restrict__ y, int64_t ldy, int64_t n, T keta, T inv_k2) {
+                  const T *__restrict__ curl, const int32_t *__restrict__ anchor_lin,
+                  const int32_t *__restrict__ soff, int K, const int32_t *__restrict__ rowptr,
+                  const int32_t *__restrict__ cols, const cx<T> *__restrict__ nearv,
+                  const cx<TX> *__restrict__ x, int64_t ldx, cx<TY> *__restrict__ y, int64_t ldy,
+                  int64_t n, T keta, T inv_k2, T eta_h) {
   using V = cx<T>;
   const int lane = threadIdx.x & 31;
   const int64_t m = (int64_t)blockIdx.x * (blockDim.x >> 5) + (threadIdx.x >> 5);
@@ -157,19 +161,30 @@ __global__ void __launch_bounds__(256)
   const int64_t a = anchor_lin[m];
   const int e0 = rowptr[m], e1 = rowptr[m + 1];
   const int r0 = blockIdx.y * RB;  // first right-hand side of this row
-  V far[RB], nr[RB];
+  V far[RB], nr[RB], fk[RB];
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb) far[rb].x = far[rb].y = nr[rb].x = nr[rb].y = 0;
+  for (int rb = 0; rb < RB; ++rb)
+    far[rb].x = far[rb].y = nr[rb].x = nr[rb].y = fk[rb].x = fk[rb].y = 0;
   for (int u = lane; u < K; u += 32) {
     const int64_t o = a + soff[u];
     const T l0 = lam[(m * 4 + 0) * K + u], l1 = lam[(m * 4 + 1) * K + u];
     const T l2 = lam[(m * 4 + 2) * K + u], l3 = lam[(m * 4 + 3) * K + u];
+    T w0 = 0, w1 = 0, w2 = 0;
+    if (CF) {
+      w0 = curl[(m * 3 + 0) * K + u];
+      w1 = curl[(m * 3 + 1) * K + u];
+      w2 = curl[(m * 3 + 2) * K + u];
+    }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
       const V *ph = phi + (int64_t)((r0 + rb) * 4) * V0 + o;
       const V p0 = ph[0], p1 = ph[V0], p2 = ph[2 * V0], p3 = ph[3 * V0];
       far[rb].x += l0 * p0.x + l1 * p1.x + l2 * p2.x - inv_k2 * l3 * p3.x;
       far[rb].y += l0 * p0.y + l1 * p1.y + l2 * p2.y - inv_k2 * l3 * p3.y;
+      if (CF) {
+        fk[rb].x += w0 * p0.x + w1 * p1.x + w2 * p2.x;
+        fk[rb].y += w0 * p0.y + w1 * p1.y + w2 * p2.y;
+      }
     }
   }
   // kNearUnroll entries per lane per pass, all gathers issued before any is
@@ -206,6 +221,10 @@ __global__ void __launch_bounds__(256)
     V acc;
     acc.x = -keta * far[rb].y + nr[rb].x;  // j k eta * far
     acc.y = keta * far[rb].x + nr[rb].y;
+    if (CF) {
+      acc.x -= eta_h * fk[rb].x;
+      acc.y -= eta_h * fk[rb].y;
+    }
     acc = half_wave_sum(acc);
     if (lane == 0) {
       cx<TY> out;
@@ -225,6 +244,16 @@ const double *lam_of<double>(const MeshDev &md) {
 template <>
 const float *lam_of<float>(const MeshDev &md) {
   return md.lam32;
+}
+template <typename T>
+const T *curl_of(const MeshDev &md);
+template <>
+const double *curl_of<double>(const MeshDev &md) {
+  return md.curl64;
+}
+template <>
+const float *curl_of<float>(const MeshDev &md) {
+  return md.curl32;
 }
 template <typename T>
 const T *plane_lam_of(const MeshDev &md);
@@ -440,20 +469,31 @@ void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, 
   const int64_t blocks = (h.n + rows_per_block - 1) / rows_per_block;
   // right-hand sides per grid row: 4 or 2 when they divide nrhs
   const int rb = nrhs % 4 == 0 ? 4 : (nrhs % 2 == 0 ? 2 : 1);
+  const bool cf = pl->cfie;
+  if (cf && (plane || !curl_of<T>(md))) throw Error(AIM_ERR_STATE, "combined field without curl weights");
   auto launch = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks, nrhs / rb), dim3(32 * rows_per_block), 0, s,
                        phi, V0, nrhs, plane ? plane_lam_of<T>(md) : lam_of<T>(md),
-                       plane ? md.plane_anchor : md.anchor_lin,
+                       cf ? curl_of<T>(md) : nullptr, plane ? md.plane_anchor : md.anchor_lin,
                        plane ? md.plane_soff : md.stencil_off, plane ? md.plane_K : h.K,
                        md.rowptr, md.cols, near_of<T>(md), x, ldx, y, ldy, h.n,
-                       (T)(h.k * kEta0), (T)(1.0 / (h.k * h.k)));
+                       (T)(pl->alpha * h.k * kEta0), (T)(1.0 / (h.k * h.k)),
+                       (T)((1.0 - pl->alpha) * kEta0));
   };
-  if (rb == 4)
-    launch(k_interp_near<T, TX, TY, 4>);
-  else if (rb == 2)
-    launch(k_interp_near<T, TX, TY, 2>);
-  else
-    launch(k_interp_near<T, TX, TY, 1>);
+  if (cf) {
+    if (rb == 4)
+      launch(k_interp_near<T, TX, TY, 4, true>);
+    else if (rb == 2)
+      launch(k_interp_near<T, TX, TY, 2, true>);
+    else
+      launch(k_interp_near<T, TX, TY, 1, true>);
+  } else if (rb == 4) {
+    launch(k_interp_near<T, TX, TY, 4, false>);
+  } else if (rb == 2) {
+    launch(k_interp_near<T, TX, TY, 2, false>);
+  } else {
+    launch(k_interp_near<T, TX, TY, 1, false>);
+  }
   LAUNCHCHECK();
   if (ev) HIPCHECK(hipEventRecord(ev[7], s));
 }

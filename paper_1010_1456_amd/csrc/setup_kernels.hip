@@ -66,6 +66,62 @@ __global__ void k_projection(const int32_t *rwg, const double *len, const double
   for (int q = 0; q < 4; ++q) lam[(b * 4 + q) * K + u] = acc[q];
 }
 
+// unit normal (v1 - v0) x (v2 - v0) of a triangle
+__device__ inline D3 tri_normal(const D3 *T) {
+  const D3 c = cross(T[1] - T[0], T[2] - T[0]);
+  return (1.0 / norm(c)) * c;
+}
+
+// l_s(xi) and its derivative for the nodes 0..M
+__device__ inline void lagrange_and_deriv(double xi, int s, int M, double *l, double *dl) {
+  double v = 1.0, dv = 0.0;
+  for (int m = 0; m <= M; ++m) {
+    if (m == s) continue;
+    const double f = 1.0 / (double)(s - m);
+    dv = dv * (xi - m) * f + v * f;  // product rule, factor by factor
+    v *= (xi - m) * f;
+  }
+  *l = v;
+  *dl = dv;
+}
+
+// Curl weights of the combined field: W[n][e][u] = sum_{T+-} A_T sum_p w_p
+// (t(r_p) x grad l_u(r_p))_e with t = f_n x n_T, so that sum_{e,u} W_e[u]
+// A_e[u] = int t . curl A for the interpolant of a grid field A.
+__global__ void k_curl_projection(const int32_t *rwg, const double *len, const double *area,
+                                  const int32_t *tris, const double *verts, const int32_t *anchor3,
+                                  int64_t n, int M, double x0, double y0, double z0, double h,
+                                  double *curl) {
+  const int K = (M + 1) * (M + 1) * (M + 1);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * K) return;
+  const int64_t b = t / K;
+  const int u = (int)(t - b * K);
+  const int sel[3] = {u / ((M + 1) * (M + 1)), (u / (M + 1)) % (M + 1), u % (M + 1)};
+  const double ax = anchor3[3 * b], ay = anchor3[3 * b + 1], az = anchor3[3 * b + 2];
+  D3 acc = d3(0, 0, 0);
+  for (int side = 0; side < 2; ++side) {
+    D3 T[3], pf;
+    double A, s, l;
+    basis_side(rwg, len, area, tris, verts, b, side, T, &A, &pf, &s, &l);
+    const D3 nt = tri_normal(T);
+    const double cf = s * l / (2.0 * A);
+    for (int p = 0; p < 7; ++p) {
+      double w;
+      const D3 r = quad_point(T, p, &w);
+      const double xi[3] = {(r.x - x0) / h - ax, (r.y - y0) / h - ay, (r.z - z0) / h - az};
+      double L[3], D[3];
+      for (int d = 0; d < 3; ++d) lagrange_and_deriv(xi[d], sel[d], M, &L[d], &D[d]);
+      const D3 g = (1.0 / h) * d3(D[0] * L[1] * L[2], L[0] * D[1] * L[2], L[0] * L[1] * D[2]);
+      const D3 tv = cross(cf * (r - pf), nt);
+      acc = acc + (A * w) * cross(tv, g);
+    }
+  }
+  curl[(b * 3 + 0) * K + u] = acc.x;
+  curl[(b * 3 + 1) * K + u] = acc.y;
+  curl[(b * 3 + 2) * K + u] = acc.z;
+}
+
 // 1 where a (basis, stencil node) pair has any non-zero weight
 __global__ void k_lam_mask(const double *lam, int64_t n, int K, uint8_t *mask) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -196,12 +252,16 @@ __global__ void k_green_table(double2 *tab, int D, double k, double h) {
 __global__ void __launch_bounds__(128)
     k_near_fill(const int32_t *rwg, const double *len, const double *area, const int32_t *tris,
                 const double *verts, const int32_t *anchor3, const int32_t *rowptr,
-                const int32_t *cols, const double *lam, const double2 *gtab, int D, int M,
-                double k, double eta, int64_t row0, double2 *nearv, double2 *zdiag) {
-  extern __shared__ double lam_m[];  // 4 * K
+                const int32_t *cols, const double *lam, const double *curl, double alpha,
+                const double2 *gtab, int D, int M, double k, double eta, int64_t row0,
+                double2 *nearv, double2 *zdiag) {
+  extern __shared__ double lam_m[];  // 4 K projection weights, then 3 K curl weights (CFIE)
   const int K = (M + 1) * (M + 1) * (M + 1);
   const int64_t m = row0 + blockIdx.x;
   for (int i = threadIdx.x; i < 4 * K; i += blockDim.x) lam_m[i] = lam[m * 4 * K + i];
+  double *w_m = lam_m + 4 * K;
+  if (curl)
+    for (int i = threadIdx.x; i < 3 * K; i += blockDim.x) w_m[i] = curl[m * 3 * K + i];
   __syncthreads();
   const double pref = k * eta;  // real factor of j k eta
   D3 Tm[2][3], pm[2];
@@ -236,15 +296,45 @@ __global__ void __launch_bounds__(128)
       }
     }
     // j k eta (zr + j zi)
-    const double mom_re = -pref * zi, mom_im = pref * zr;
+    double mom_re = -pref * zi, mom_im = pref * zr;
+    if (curl) {
+      // combined field: alpha Z^E + (1 - alpha) eta (G/2 - K) over the four
+      // triangle pairs (coplanar pairs, the same triangle included, have K = 0)
+      double hr = 0.0, hi = 0.0;
+      for (int sn_ = 0; sn_ < 2; ++sn_) {
+        D3 Tn[3], pn;
+        double An, sn, ln;
+        basis_side(rwg, len, area, tris, verts, n, sn_, Tn, &An, &pn, &sn, &ln);
+        const int tn = rwg[4 * n + sn_];
+        const int32_t *vn = &tris[3 * (int64_t)tn];
+        for (int sm_ = 0; sm_ < 2; ++sm_) {
+          const double f = sm[sm_] * sn * lm * ln / (4.0 * Am[sm_] * An);
+          if (tm_id[sm_] == tn) {
+            hr += f * 0.5 * gram_pair(Tm[sm_], Am[sm_], pm[sm_], pn);
+            continue;
+          }
+          if (coplanar(Tm[sm_], Tn)) continue;
+          const int32_t *vm = &tris[3 * (int64_t)tm_id[sm_]];
+          bool touch = false;
+          for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) touch |= (vm[a] == vn[c]);
+          const C2 I = mfie_pair(Tm[sm_], Am[sm_], pm[sm_], tri_normal(Tm[sm_]), Tn, An, pn, k, touch);
+          hr -= f * I.re;
+          hi -= f * I.im;
+        }
+      }
+      mom_re = alpha * mom_re + (1.0 - alpha) * eta * hr;
+      mom_im = alpha * mom_im + (1.0 - alpha) * eta * hi;
+    }
     // ---- Z^grid_mn = j k eta [sum_{q<3} L_mq^T G L_nq - k^-2 L_md^T G L_nd]
     const int dn[3] = {am[0] - anchor3[3 * n], am[1] - anchor3[3 * n + 1], am[2] - anchor3[3 * n + 2]};
     const double *lam_n = lam + n * 4 * K;
-    double gr = 0.0, gi = 0.0;
+    double gr = 0.0, gi = 0.0, wr = 0.0, wi = 0.0;
     for (int v = 0; v < K; ++v) {
       const int vi = v / (M1 * M1), vj = (v / M1) % M1, vk = v % M1;
       const double ln0 = lam_n[v], ln1 = lam_n[K + v], ln2 = lam_n[2 * K + v], ln3 = lam_n[3 * K + v];
       double tr0 = 0, ti0 = 0, tr1 = 0, ti1 = 0;  // vector and scalar parts
+      double tr2 = 0, ti2 = 0;                    // curl-weight part (combined field)
       for (int u = 0; u < K; ++u) {
         const int ui = u / (M1 * M1), uj = (u / M1) % M1, uk = u % M1;
         const int oi = abs(dn[0] + ui - vi), oj = abs(dn[1] + uj - vj), ok = abs(dn[2] + uk - vk);
@@ -255,11 +345,22 @@ __global__ void __launch_bounds__(128)
         ti0 += g.y * vec;
         tr1 += g.x * sca;
         ti1 += g.y * sca;
+        if (curl) {
+          const double cw = w_m[u] * ln0 + w_m[K + u] * ln1 + w_m[2 * K + u] * ln2;
+          tr2 += g.x * cw;
+          ti2 += g.y * cw;
+        }
       }
       gr += tr0 - tr1 / (k * k);
       gi += ti0 - ti1 / (k * k);
+      wr += tr2;
+      wi += ti2;
     }
-    const double grid_re = -pref * gi, grid_im = pref * gr;
+    double grid_re = -pref * gi, grid_im = pref * gr;
+    if (curl) {  // alpha j k eta [..] - (1 - alpha) eta W^T g Lambda
+      grid_re = alpha * grid_re - (1.0 - alpha) * eta * wr;
+      grid_im = alpha * grid_im - (1.0 - alpha) * eta * wi;
+    }
     nearv[e] = make_double2(mom_re - grid_re, mom_im - grid_im);
     if (n == m) zdiag[m] = make_double2(mom_re, mom_im);
   }
@@ -268,23 +369,26 @@ __global__ void __launch_bounds__(128)
 __global__ void k_excitation(const int32_t *rwg, const double *len, const double *area,
                              const int32_t *tris, const double *verts, int64_t n, double k,
                              const double *wv /* per wave: khat(3), pol(3) */, int nw,
-                             double2 *b, int64_t ldb) {
+                             double alpha, bool cfie, double2 *b, int64_t ldb) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * nw) return;
   const int w = (int)(t / n);
   const int64_t m = t - (int64_t)w * n;
   const D3 kh = d3(wv[6 * w], wv[6 * w + 1], wv[6 * w + 2]);
   const D3 ph = d3(wv[6 * w + 3], wv[6 * w + 4], wv[6 * w + 5]);
+  const D3 hd = cross(kh, ph);  // eta H_inc direction
   double vr = 0.0, vi = 0.0;
   for (int side = 0; side < 2; ++side) {
     D3 T[3], pf;
     double A, s, l;
     basis_side(rwg, len, area, tris, verts, m, side, T, &A, &pf, &s, &l);
     const double cf = s * l / (2.0 * A);
+    // tested field direction: p_hat (EFIE); alpha p_hat + (1 - alpha) n x (k_hat x p_hat) (CFIE)
+    const D3 dir = cfie ? alpha * ph + (1.0 - alpha) * cross(tri_normal(T), hd) : ph;
     for (int p = 0; p < 7; ++p) {
       double wq;
       const D3 r = quad_point(T, p, &wq);
-      const double fp = cf * dot(r - pf, ph);
+      const double fp = cf * dot(r - pf, dir);
       double sn, cs;
       sincos(k * dot(kh, r), &sn, &cs);  // exp(-j k khat.r)
       vr += A * wq * fp * cs;
@@ -370,6 +474,19 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
     hipLaunchKernelGGL(k_to_float, dim3(blocks_for(n * 4 * K, 256)), dim3(256), 0, s, md.lam64,
                        md.lam32, n * 4 * K);
     LAUNCHCHECK();
+  }
+  if (pl->cfie) {  // curl weights of the MFIE part
+    md.curl64 = (double *)dev_alloc(pl, sizeof(double) * n * 3 * K);
+    hipLaunchKernelGGL(k_curl_projection, dim3(blocks_for(n * K, 256)), dim3(256), 0, s, md.rwg,
+                       md.len, area, md.tris, md.verts, anchor3, n, M, h.x0[0], h.x0[1], h.x0[2],
+                       h.h, md.curl64);
+    LAUNCHCHECK();
+    if (pl->mixed) {
+      md.curl32 = (float *)dev_alloc(pl, sizeof(float) * n * 3 * K);
+      hipLaunchKernelGGL(k_to_float, dim3(blocks_for(n * 3 * K, 256)), dim3(256), 0, s, md.curl64,
+                         md.curl32, n * 3 * K);
+      LAUNCHCHECK();
+    }
   }
 
   // a flat scatterer lying in one grid plane: every projection weight on
@@ -524,9 +641,10 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
   const int64_t chunk = 1 << 20;  // rows per launch
   for (int64_t r0 = 0; r0 < n; r0 += chunk) {
     const int64_t rows = std::min(chunk, n - r0);
-    hipLaunchKernelGGL(k_near_fill, dim3((unsigned)rows), dim3(128), sizeof(double) * 4 * K, s,
-                       md.rwg, md.len, area, md.tris, md.verts, anchor3, md.rowptr, md.cols,
-                       md.lam64, gtab, D, M, h.k, kEta0, r0, md.near64, md.zdiag);
+    hipLaunchKernelGGL(k_near_fill, dim3((unsigned)rows), dim3(128),
+                       sizeof(double) * (pl->cfie ? 7 : 4) * K, s, md.rwg, md.len, area, md.tris,
+                       md.verts, anchor3, md.rowptr, md.cols, md.lam64, md.curl64, pl->alpha, gtab,
+                       D, M, h.k, kEta0, r0, md.near64, md.zdiag);
     LAUNCHCHECK();
   }
   if (pl->mixed) {
@@ -566,7 +684,7 @@ void excitation_mesh(Plan *pl, MeshDev &md, int nw, const aim_planewave *w, doub
   double *dwv = upload(pl, wv.data(), wv.size(), s);
   const int64_t n = md.hp.n;
   hipLaunchKernelGGL(k_excitation, dim3(blocks_for(n * nw, 256)), dim3(256), 0, s, md.rwg, md.len,
-                     md.area, md.tris, md.verts, n, md.hp.k, dwv, nw, b, ldb);
+                     md.area, md.tris, md.verts, n, md.hp.k, dwv, nw, pl->alpha, pl->cfie, b, ldb);
   LAUNCHCHECK();
   HIPCHECK(hipStreamSynchronize(s));
   dev_free(pl, dwv);

@@ -144,3 +144,26 @@ def test_binding_layouts_and_constants_match_header(tmp_path):
         if hasattr(lib_aim, name):
             assert getattr(lib_aim, name) == int(val), name
     assert lib_aim.SETUP_PHASES[lib_aim.AIM_NSETUP - 1] == "tune"
+
+
+def test_cfie_needs_a_closed_outward_mesh():
+    """The combined field is accepted on a closed, outward-oriented sphere and
+    refused on an open plate, on an inside-out sphere, on a sphere with one
+    triangle flipped, and for alpha outside [0, 1]; the EFIE takes them all."""
+    m = sphere_mesh(0.5, 0.3e9, nf=3)
+    hp = lib_aim.host_plan(m.verts, m.tris, m.freq_hz, cfie_alpha=0.6)
+    assert hp["n"] == 3 * m.tris.shape[0] // 2
+    flipped_all = m.tris[:, ::-1].copy()
+    flipped_one = m.tris.copy()
+    flipped_one[5] = flipped_one[5, ::-1]
+    p = plate_mesh(1.0, 0.3e9)
+    bad = [(p.verts, p.tris, 0.6, lib_aim.AIM_ERR_MESH),
+           (m.verts, flipped_all, 0.6, lib_aim.AIM_ERR_MESH),
+           (m.verts, flipped_one, 0.6, lib_aim.AIM_ERR_MESH),
+           (m.verts, m.tris, 1.5, lib_aim.AIM_ERR_ARG),
+           (m.verts, m.tris, -0.1, lib_aim.AIM_ERR_ARG)]
+    for verts, tris, alpha, status in bad:
+        with pytest.raises(lib_aim.AimError) as e:
+            lib_aim.host_plan(verts, tris, m.freq_hz, cfie_alpha=alpha)
+        assert e.value.status == status
+        lib_aim.host_plan(verts, tris, m.freq_hz)
