@@ -542,6 +542,15 @@ def main(argv=None):
     }
     if args.solve_iters > 0:
         out["solve"] = solve_compare(plan, A, mesh, args.workload, args.solve_iters)
+        if args.workload.startswith("sphere") and args.cfie is None:
+            # the paper's formulation for the closed sphere: CFIE, alpha = 0.6
+            log("[bench] CFIE (alpha 0.6) plan for the solve comparison")
+            plan_c = A.Plan([(m.verts, m.tris, m.freq_hz) for m in meshes], h_lambda=cfg["h_lambda"],
+                            order=cfg["order"], near_radius_lambda=cfg["near_radius_lambda"],
+                            cfie_alpha=0.6)
+            out["solve_cfie"] = solve_compare(plan_c, A, mesh, args.workload, args.solve_iters)
+            out["solve_cfie"]["setting"] = "CFIE alpha 0.6; " + out["solve_cfie"]["setting"]
+            plan_c.close()
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(mesh, cfg, R, tuple(info["pad"][0]), args.cfie)
