@@ -34,7 +34,9 @@ constexpr int anterp_threads() {
   return t < 256 ? 256 : (t > 1024 ? 1024 : t);
 }
 
-template <typename T, typename TX, class PC>
+// PR: at most P/2 grid nodes per line, so the first stage runs the
+// upper-half-zero DFT (even first radix)
+template <typename T, typename TX, bool PR, class PC>
 __global__ void __launch_bounds__((anterp_threads<T, PC>()))
     k_anterp_fftz(const cx<TX> *__restrict__ x, int64_t ldx, int nrhs,
                   const int32_t *__restrict__ node_ptr, const int32_t *__restrict__ ent_col,
@@ -120,10 +122,14 @@ __global__ void __launch_bounds__((anterp_threads<T, PC>()))
         if constexpr (last) gout[i] = v;
         else ll[i] = v;
       };
+      constexpr bool uz = stage_uz<R, false, PR, first, last>();
       V v[R];
-      if (active) stage_load<R, false, V>(v, beta, Mp, ld);
+      if (active) {
+        if constexpr (uz) stage_load_p<R, R / 2, V>(v, beta, Mp, ld);
+        else stage_load<R, false, V>(v, beta, Mp, ld);
+      }
       if constexpr (!last) __syncthreads();
-      if (active) stage_compute_store<R, false, V>(v, beta, L, Mp, twl, st);
+      if (active) stage_compute_store_p<R, false, uz, R, false>(v, beta, L, Mp, twl, st);
       if constexpr (!last) __syncthreads();
     });
   }
@@ -144,8 +150,14 @@ bool launch_anterp_fftz(const cx<TX> *x, int64_t ldx, int nrhs, const int32_t *n
   const size_t lds = ((size_t)4 * LB * (PC::P + 1) + PC::P + (size_t)(threads / 64) * 256) *
                      sizeof(cx<T>);
   const int64_t blocks = (nlines + LB - 1) / LB;
-  hipLaunchKernelGGL((k_anterp_fftz<T, TX, PC>), dim3((unsigned)blocks), dim3(threads), lds, s, x,
-                     ldx, nrhs, node_ptr, ent_col, lamT, Nz, nlines, out, out_ls, out_fstride, tw);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), lds, s, x, ldx, nrhs, node_ptr,
+                       ent_col, lamT, Nz, nlines, out, out_ls, out_fstride, tw);
+  };
+  if (pass_prunable<PC>(false, Nz, 0))
+    go(k_anterp_fftz<T, TX, true, PC>);
+  else
+    go(k_anterp_fftz<T, TX, false, PC>);
   LAUNCHCHECK();
   return true;
   }

@@ -99,7 +99,25 @@ constexpr int threads_contig() {
   return round_up_c(PC::maxnb() * tile_contig<T, PC>(), 64);
 }
 
-template <typename T, bool INV, class PC>
+// PR (pruned): a forward pass whose lines hold at most P/2 inputs runs its
+// first stage as the upper-half-zero DFT; an inverse pass that keeps at most
+// P/2 outputs computes only the lower half of its last stage's outputs (both
+// need an even radix there).
+template <int R, bool INV, bool PR, bool FIRST, bool LAST>
+constexpr bool stage_uz() {
+  return PR && !INV && FIRST && R % 2 == 0;
+}
+template <int R, bool INV, bool PR, bool FIRST, bool LAST>
+constexpr int stage_nout() {
+  return (PR && INV && LAST && R % 2 == 0) ? R / 2 : R;
+}
+template <class PC>
+bool pass_prunable(bool inverse, int n_in, int n_out) {
+  return inverse ? (PC::r(PC::ns - 1) % 2 == 0 && 2 * n_out <= PC::P)
+                 : (PC::r(0) % 2 == 0 && 2 * n_in <= PC::P);
+}
+
+template <typename T, bool INV, bool PR, class PC>
 __global__ void __launch_bounds__((threads_contig<T, PC>()))
     k_fft_contig(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, int n_in, int n_out,
                  int64_t lines, ContigMap imap, ContigMap omap, const cx<T> *__restrict__ tw,
@@ -135,15 +153,20 @@ __global__ void __launch_bounds__((threads_contig<T, PC>()))
         ll[i] = v;
       }
     };
+    constexpr bool uz = stage_uz<R, INV, PR, first, last>();
+    constexpr int nout = stage_nout<R, INV, PR, first, last>();
     V v[R];
-    if (active) stage_load<R, INV, V>(v, beta, Mp, ld);
+    if (active) {
+      if constexpr (uz) stage_load_p<R, R / 2, V>(v, beta, Mp, ld);
+      else stage_load<R, INV, V>(v, beta, Mp, ld);
+    }
     if constexpr (!first && !last) __syncthreads();
-    if (active) stage_compute_store<R, INV, V>(v, beta, L, Mp, twl, st);
+    if (active) stage_compute_store_p<R, INV, uz, nout, false>(v, beta, L, Mp, twl, st);
     if constexpr (!last) __syncthreads();
   });
 }
 
-template <typename T, bool INV, class PC>
+template <typename T, bool INV, bool PR, class PC>
 __global__ void __launch_bounds__((threads_strided<T, PC>()))
     k_fft_strided(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, int n_in, int n_out,
                   int64_t inner, int ntile, LineMap imap, LineMap omap,
@@ -187,10 +210,15 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
         lds[i * B + b] = v;
       }
     };
+    constexpr bool uz = stage_uz<R, INV, PR, first, last>();
+    constexpr int nout = stage_nout<R, INV, PR, first, last>();
     V v[R];
-    if (active) stage_load<R, INV, V>(v, beta, Mp, ld);
+    if (active) {
+      if constexpr (uz) stage_load_p<R, R / 2, V>(v, beta, Mp, ld);
+      else stage_load<R, INV, V>(v, beta, Mp, ld);
+    }
     if constexpr (!first && !last) __syncthreads();
-    if (active) stage_compute_store<R, INV, V>(v, beta, L, Mp, twl, st);
+    if (active) stage_compute_store_p<R, INV, uz, nout, false>(v, beta, L, Mp, twl, st);
     if constexpr (!last) __syncthreads();
   });
 }
@@ -474,12 +502,15 @@ void launch_contig(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t lin
   constexpr int threads = threads_contig<T, PC>();
   const size_t lds = PC::ns > 1 ? ((size_t)B * (PC::P + 1) + PC::P) * sizeof(cx<T>) : 0;
   const int64_t blocks = (lines + B - 1) / B;
+  const bool pr = pass_prunable<PC>(inverse, n_in, n_out);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), lds, s, in, out, n_in, n_out,
+                       lines, imap, omap, tw, B);
+  };
   if (inverse)
-    hipLaunchKernelGGL((k_fft_contig<T, true, PC>), dim3((unsigned)blocks), dim3(threads), lds, s,
-                       in, out, n_in, n_out, lines, imap, omap, tw, B);
+    pr ? go(k_fft_contig<T, true, true, PC>) : go(k_fft_contig<T, true, false, PC>);
   else
-    hipLaunchKernelGGL((k_fft_contig<T, false, PC>), dim3((unsigned)blocks), dim3(threads), lds, s,
-                       in, out, n_in, n_out, lines, imap, omap, tw, B);
+    pr ? go(k_fft_contig<T, false, true, PC>) : go(k_fft_contig<T, false, false, PC>);
   LAUNCHCHECK();
 }
 
@@ -492,12 +523,15 @@ void launch_strided(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t ou
   const int ntile = (int)((inner + B - 1) / B);
   const size_t lds = PC::ns > 1 ? (size_t)PC::P * (B + 1) * sizeof(cx<T>) : 0;
   const int64_t blocks = outer * ntile;
+  const bool pr = pass_prunable<PC>(inverse, n_in, n_out);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), lds, s, in, out, n_in, n_out,
+                       inner, ntile, imap, omap, tw, B);
+  };
   if (inverse)
-    hipLaunchKernelGGL((k_fft_strided<T, true, PC>), dim3((unsigned)blocks), dim3(threads), lds, s,
-                       in, out, n_in, n_out, inner, ntile, imap, omap, tw, B);
+    pr ? go(k_fft_strided<T, true, true, PC>) : go(k_fft_strided<T, true, false, PC>);
   else
-    hipLaunchKernelGGL((k_fft_strided<T, false, PC>), dim3((unsigned)blocks), dim3(threads), lds, s,
-                       in, out, n_in, n_out, inner, ntile, imap, omap, tw, B);
+    pr ? go(k_fft_strided<T, false, true, PC>) : go(k_fft_strided<T, false, false, PC>);
   LAUNCHCHECK();
 }
 
