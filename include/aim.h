@@ -107,6 +107,11 @@ typedef struct {
  * right-hand side V = alpha <f, E_inc> + (1 - alpha) <f, n x (k_hat x E_inc)>)
  * and the Jacobi preconditioner then use the combined operator. */
 #define AIM_FLAG_CFIE 2
+/* As the paper does for a mixed set of scatterers (Section 2.2: EFIE for the
+ * open plate, CFIE for the closed bodies): the combined field with
+ * cfie_alpha on every mesh that is closed, consistently oriented and of
+ * positive volume, the EFIE on the others (no mesh is refused for it). */
+#define AIM_FLAG_CFIE_CLOSED 4
 
 /* Device memory provider. alloc returns device memory of >= bytes (NULL on
  * failure), ordered on `stream`; free releases it. Passing NULL for the
@@ -171,7 +176,8 @@ typedef struct {
                                                near-zone fill (FP64 quadrature of Z^MOM - Z^grid),
                                                variant tuning (paper Section 2.4, Fig. 4, times
                                                the matrix fill) */
-  double cfie_alpha;                    /* combined-field parameter, or -1 for the EFIE */
+  double cfie_alpha[AIM_MAX_MESH];      /* combined-field parameter of each mesh, or -1 where
+                                           the mesh uses the EFIE */
 } aim_info;
 
 /* GMRES options. restart m (<= 200), relative-residual tolerance on

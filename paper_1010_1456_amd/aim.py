@@ -30,6 +30,7 @@ AIM_MIXED_IO64 = 2
 AIM_NSTAGE = 7
 AIM_FLAG_NO_MIXED = 1
 AIM_FLAG_CFIE = 2
+AIM_FLAG_CFIE_CLOSED = 4
 AIM_SOLVE_NO_GRAPH = 1
 AIM_MAX_MESH = 16
 AIM_DATA_LAMBDA64 = 1
@@ -86,7 +87,7 @@ class AimInfo(ctypes.Structure):
                 ("bytes_fp64", c_double * M), ("bytes_mixed", c_double * M),
                 ("fused_projection", (c_int32 * 2) * M), ("planar_z", c_int32 * M),
                 ("device_bytes", c_double), ("setup_ms", (c_double * AIM_NSETUP) * M),
-                ("cfie_alpha", c_double)]
+                ("cfie_alpha", c_double * M)]
 
 
 class AimSolveOpts(ctypes.Structure):
@@ -157,9 +158,10 @@ def _mesh_struct(verts, tris, freq_hz, keep):
                    t.ctypes.data_as(POINTER(c_int32)), float(freq_hz))
 
 
-def _params(h_lambda, order, near_radius_lambda, fft_min_pad=0, flags=0, cfie_alpha=None):
+def _params(h_lambda, order, near_radius_lambda, fft_min_pad=0, flags=0, cfie_alpha=None,
+            cfie_closed_only=False):
     if cfie_alpha is not None:
-        flags |= AIM_FLAG_CFIE
+        flags |= AIM_FLAG_CFIE_CLOSED if cfie_closed_only else AIM_FLAG_CFIE
     return AimParams(float(h_lambda), int(order), int(fft_min_pad), float(near_radius_lambda),
                      int(flags), 0, float(cfie_alpha) if cfie_alpha is not None else 0.0)
 
@@ -172,12 +174,13 @@ def _waves(waves):
 
 
 def host_plan(verts, tris, freq_hz, h_lambda=0.1, order=2, near_radius_lambda=0.3, fft_min_pad=0,
-              cfie_alpha=None):
+              cfie_alpha=None, cfie_closed_only=False):
     """Host phase only (no GPU): RWG table, anchors, near-zone CSR, grid."""
     L = lib()
     keep = []
     m = _mesh_struct(verts, tris, freq_hz, keep)
-    p = _params(h_lambda, order, near_radius_lambda, fft_min_pad, cfie_alpha=cfie_alpha)
+    p = _params(h_lambda, order, near_radius_lambda, fft_min_pad, cfie_alpha=cfie_alpha,
+                cfie_closed_only=cfie_closed_only)
     hp = c_void_p()
     _check(L.aim_host_plan_build(ctypes.byref(m), ctypes.byref(p), ctypes.byref(hp)))
     try:
@@ -233,7 +236,7 @@ class Plan:
     meshes: list of (verts (nv,3) metres, tris (nt,3), freq_hz)."""
 
     def __init__(self, meshes, h_lambda=0.1, order=2, near_radius_lambda=0.3, fft_min_pad=0,
-                 mixed=True, stream=None, cfie_alpha=None):
+                 mixed=True, stream=None, cfie_alpha=None, cfie_closed_only=False):
         import torch
 
         self._torch = torch
@@ -247,7 +250,7 @@ class Plan:
         for i, (v, t, f) in enumerate(meshes):
             arr[i] = _mesh_struct(v, t, f, keep)
         p = _params(h_lambda, order, near_radius_lambda, fft_min_pad, 0 if mixed else AIM_FLAG_NO_MIXED,
-                    cfie_alpha)
+                    cfie_alpha, cfie_closed_only)
         self._alloc = TorchAllocator(self.device)
         h = c_void_p()
         _check(L.aim_setup(arr, len(meshes), ctypes.byref(p), ctypes.byref(self._alloc.struct),
@@ -286,7 +289,7 @@ class Plan:
             planar_z=[inf.planar_z[i] for i in range(nm)],
             device_bytes=inf.device_bytes,
             setup_ms=[dict(zip(SETUP_PHASES, inf.setup_ms[i])) for i in range(nm)],
-            cfie_alpha=None if inf.cfie_alpha < 0 else inf.cfie_alpha)
+            cfie_alpha=[None if inf.cfie_alpha[i] < 0 else inf.cfie_alpha[i] for i in range(nm)])
 
     def _stream(self, stream):
         s = stream if stream is not None else self._torch.cuda.current_stream()

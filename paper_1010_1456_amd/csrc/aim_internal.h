@@ -52,6 +52,10 @@ struct HostPlan {
   int64_t nv = 0, nt = 0, n = 0, nnz = 0;
   double freq = 0, lam = 0, k = 0, h = 0, r_near = 0;
   int order = 2, K = 27;
+  // formulation: the combined field (alpha EFIE + (1 - alpha) eta MFIE) on
+  // this mesh, else the EFIE (alpha = 1)
+  bool cfie = false;
+  double alpha = 1.0;
   std::vector<double> verts;     // nv*3
   std::vector<int32_t> tris;     // nt*3
   std::vector<double> area;      // nt
@@ -174,8 +178,6 @@ struct Plan {
   hipStream_t setup_stream = nullptr;
   aim_params params{};
   bool mixed = true;
-  bool cfie = false;    // combined-field equation (alpha EFIE + (1 - alpha) eta MFIE)
-  double alpha = 1.0;   // its parameter
   int nmesh = 0;
   int64_t n_total = 0;
   std::vector<MeshDev> mesh;

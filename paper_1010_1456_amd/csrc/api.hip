@@ -176,8 +176,6 @@ aim_status aim_setup(const aim_mesh *meshes, int32_t nmesh, const aim_params *p,
   pl->setup_stream = (hipStream_t)hip_stream;
   pl->params = *p;
   pl->mixed = !(p->flags & AIM_FLAG_NO_MIXED);
-  pl->cfie = (p->flags & AIM_FLAG_CFIE) != 0;
-  pl->alpha = pl->cfie ? p->cfie_alpha : 1.0;
   pl->nmesh = nmesh;
   pl->mesh.resize(nmesh);
   aim_status st = guarded([&] {
@@ -232,7 +230,7 @@ aim_status aim_plan_info(const aim_plan *plan, aim_info *out) {
     out->fused_projection[i][0] = md.fuse_proj[0];
     out->fused_projection[i][1] = md.fuse_proj[1];
     out->planar_z[i] = md.planar_z;
-    out->cfie_alpha = plan->cfie ? plan->alpha : -1.0;
+    out->cfie_alpha[i] = md.hp.cfie ? md.hp.alpha : -1.0;
     for (int j = 0; j < AIM_NSETUP; ++j) out->setup_ms[i][j] = md.setup_ms[j];
   }
   out->device_bytes = plan->device_bytes;

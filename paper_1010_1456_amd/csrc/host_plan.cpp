@@ -59,8 +59,10 @@ void host_plan_build(const aim_mesh &m, const aim_params &p, HostPlan *hp) {
   if (!(p.h_lambda > 0)) fail_arg("h_lambda must be > 0");
   if (p.order < 1 || p.order > 5) fail_arg("order must be in 1..5");
   if (!(p.near_radius_lambda >= 0)) fail_arg("near_radius_lambda must be >= 0");
-  const bool cfie = (p.flags & AIM_FLAG_CFIE) != 0;
-  if (cfie && !(p.cfie_alpha >= 0.0 && p.cfie_alpha <= 1.0)) fail_arg("cfie_alpha must be in [0, 1]");
+  const bool cfie_all = (p.flags & AIM_FLAG_CFIE) != 0;
+  const bool cfie_closed = (p.flags & AIM_FLAG_CFIE_CLOSED) != 0;
+  if ((cfie_all || cfie_closed) && !(p.cfie_alpha >= 0.0 && p.cfie_alpha <= 1.0))
+    fail_arg("cfie_alpha must be in [0, 1]");
   if (m.nv > INT32_MAX || m.nt > INT32_MAX) fail_arg("mesh too large");
 
   HostPlan &h = *hp;
@@ -129,7 +131,7 @@ void host_plan_build(const aim_mesh &m, const aim_params &p, HostPlan *hp) {
   }
   const int64_t n = (int64_t)h.e_lo.size();
   if (n == 0) fail_mesh("mesh has no interior edge");
-  if (cfie) {
+  if (cfie_all || cfie_closed) {
     // enclosed volume sum v0 . (v1 x v2) / 6 > 0 for outward normals
     double vol = 0.0;
     for (int64_t t = 0; t < nt; ++t) {
@@ -138,9 +140,12 @@ void host_plan_build(const aim_mesh &m, const aim_params &p, HostPlan *hp) {
       vol += A[0] * (B[1] * C[2] - B[2] * C[1]) + A[1] * (B[2] * C[0] - B[0] * C[2]) +
              A[2] * (B[0] * C[1] - B[1] * C[0]);
     }
-    if (!closed || !(vol > 0.0))
+    const bool outward = closed && vol > 0.0;
+    if (cfie_all && !outward)
       fail_mesh("the combined-field equation needs a closed, consistently oriented mesh with "
                 "outward normals");
+    h.cfie = outward;
+    h.alpha = outward ? p.cfie_alpha : 1.0;
   }
   h.n = n;
   h.len.resize(n);

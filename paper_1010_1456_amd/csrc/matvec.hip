@@ -469,7 +469,7 @@ void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, 
   const int64_t blocks = (h.n + rows_per_block - 1) / rows_per_block;
   // right-hand sides per grid row: 4 or 2 when they divide nrhs
   const int rb = nrhs % 4 == 0 ? 4 : (nrhs % 2 == 0 ? 2 : 1);
-  const bool cf = pl->cfie;
+  const bool cf = h.cfie;
   if (cf && (plane || !curl_of<T>(md))) throw Error(AIM_ERR_STATE, "combined field without curl weights");
   auto launch = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks, nrhs / rb), dim3(32 * rows_per_block), 0, s,
@@ -477,8 +477,8 @@ void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, 
                        cf ? curl_of<T>(md) : nullptr, plane ? md.plane_anchor : md.anchor_lin,
                        plane ? md.plane_soff : md.stencil_off, plane ? md.plane_K : h.K,
                        md.rowptr, md.cols, near_of<T>(md), x, ldx, y, ldy, h.n,
-                       (T)(pl->alpha * h.k * kEta0), (T)(1.0 / (h.k * h.k)),
-                       (T)((1.0 - pl->alpha) * kEta0));
+                       (T)(h.alpha * h.k * kEta0), (T)(1.0 / (h.k * h.k)),
+                       (T)((1.0 - h.alpha) * kEta0));
   };
   if (cf) {
     if (rb == 4)

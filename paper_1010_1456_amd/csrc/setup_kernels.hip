@@ -475,7 +475,7 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
                        md.lam32, n * 4 * K);
     LAUNCHCHECK();
   }
-  if (pl->cfie) {  // curl weights of the MFIE part
+  if (h.cfie) {  // curl weights of the MFIE part
     md.curl64 = (double *)dev_alloc(pl, sizeof(double) * n * 3 * K);
     hipLaunchKernelGGL(k_curl_projection, dim3(blocks_for(n * K, 256)), dim3(256), 0, s, md.rwg,
                        md.len, area, md.tris, md.verts, anchor3, n, M, h.x0[0], h.x0[1], h.x0[2],
@@ -642,8 +642,8 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
   for (int64_t r0 = 0; r0 < n; r0 += chunk) {
     const int64_t rows = std::min(chunk, n - r0);
     hipLaunchKernelGGL(k_near_fill, dim3((unsigned)rows), dim3(128),
-                       sizeof(double) * (pl->cfie ? 7 : 4) * K, s, md.rwg, md.len, area, md.tris,
-                       md.verts, anchor3, md.rowptr, md.cols, md.lam64, md.curl64, pl->alpha, gtab,
+                       sizeof(double) * (h.cfie ? 7 : 4) * K, s, md.rwg, md.len, area, md.tris,
+                       md.verts, anchor3, md.rowptr, md.cols, md.lam64, md.curl64, h.alpha, gtab,
                        D, M, h.k, kEta0, r0, md.near64, md.zdiag);
     LAUNCHCHECK();
   }
@@ -684,7 +684,8 @@ void excitation_mesh(Plan *pl, MeshDev &md, int nw, const aim_planewave *w, doub
   double *dwv = upload(pl, wv.data(), wv.size(), s);
   const int64_t n = md.hp.n;
   hipLaunchKernelGGL(k_excitation, dim3(blocks_for(n * nw, 256)), dim3(256), 0, s, md.rwg, md.len,
-                     md.area, md.tris, md.verts, n, md.hp.k, dwv, nw, pl->alpha, pl->cfie, b, ldb);
+                     md.area, md.tris, md.verts, n, md.hp.k, dwv, nw, md.hp.alpha, md.hp.cfie, b,
+                     ldb);
   LAUNCHCHECK();
   HIPCHECK(hipStreamSynchronize(s));
   dev_free(pl, dwv);

@@ -71,7 +71,7 @@ def test_operator_data(name):
     from paper_1010_1456_amd import aim as A
 
     c = case(name)
-    assert c.plan.info()["cfie_alpha"] == c.alpha
+    assert c.plan.info()["cfie_alpha"] == [c.alpha]
     W = c.plan.export(0, A.AIM_DATA_CURL64)
     assert np.abs(W - c.op.curl).max() <= 1e-13 * np.abs(c.op.curl).max()
     near = c.plan.export(0, A.AIM_DATA_NEAR64)
@@ -155,3 +155,33 @@ def test_cfie_converges_faster_than_efie_on_a_larger_sphere():
         plan.close()
     _log(f"[cfie vs efie, 2-lambda sphere] EFIE its/err {out[None][:2]}, CFIE its/err {out[0.6][:2]}")
     assert out[0.6][2] and out[0.6][0] < out[None][0]
+
+
+def test_batch_with_the_papers_formulations():
+    """A plate and a sphere in one plan with the combined field on closed
+    meshes only: the plate takes the EFIE, the sphere the CFIE, and the
+    batched product and solve equal those of the single-mesh plans."""
+    from paper_1010_1456_amd import aim as A
+    from workloads import plate_mesh
+
+    plate = plate_mesh(2.0, 0.3e9, jitter_seed=1001)
+    sph = sphere_mesh(0.5, 0.3e9, nf=4)
+    batch = A.Plan([(m.verts, m.tris, m.freq_hz) for m in (plate, sph)], cfie_alpha=0.6,
+                   cfie_closed_only=True)
+    inf = batch.info()
+    assert inf["cfie_alpha"] == [None, 0.6]
+    singles = [A.Plan([(plate.verts, plate.tris, plate.freq_hz)]),
+               A.Plan([(sph.verts, sph.tris, sph.freq_hz)], cfie_alpha=0.6)]
+    x = random_current(inf["n_total"], nrhs=2, seed=31)
+    y = batch.matvec(torch.from_numpy(x).cuda(), A.AIM_FP64).cpu().numpy()
+    waves = [(0.0, 0.0, 0), (0.7, 0.3, 1)]
+    xb, stb = batch.solve(waves, A.AIM_MIXED, tol=1e-6)
+    xb = xb.cpu().numpy()
+    for i, pl in enumerate(singles):
+        lo, n = inf["offset"][i], inf["n"][i]
+        ys = pl.matvec(torch.from_numpy(np.ascontiguousarray(x[:, lo:lo + n])).cuda(), A.AIM_FP64).cpu().numpy()
+        assert rel(y[:, lo:lo + n], ys) <= 1e-13
+        xs, sts = pl.solve(waves, A.AIM_MIXED, tol=1e-6)
+        assert rel(xb[:, lo:lo + n], xs.cpu().numpy()) <= 1e-5
+        pl.close()
+    batch.close()
