@@ -132,6 +132,11 @@ struct MeshDev {
   // with its basis index and its 4 weights (x, y, z, div)
   int64_t n_entries = 0;
   int32_t *node_ptr = nullptr;  // V0 + 1
+  // the nodes with at least one entry (occupied: on the scatterer's stencils)
+  // and their entry ranges, occ_ptr[i] .. occ_ptr[i + 1] - 1
+  int64_t n_occ = 0;
+  int32_t *occ = nullptr;      // n_occ node indices, increasing
+  int32_t *occ_ptr = nullptr;  // n_occ + 1
   int32_t *ent_col = nullptr;   // n_entries
   double *lamT64 = nullptr;     // n_entries * 4
   float *lamT32 = nullptr;      // n_entries * 4
@@ -149,6 +154,9 @@ struct MeshDev {
   // node-ordered entries (ent_col, lamT shared), in-plane stencils of
   // (M+1)^2 weights, plane-linear anchors and stencil offsets
   int32_t *plane_node_ptr = nullptr;  // Nx Ny + 1
+  int64_t n_plane_occ = 0;            // occupied plane nodes and their entry ranges
+  int32_t *plane_occ = nullptr;
+  int32_t *plane_occ_ptr = nullptr;
   double *plane_lam64 = nullptr;      // n * 4 * (M+1)^2
   float *plane_lam32 = nullptr;
   int32_t *plane_anchor = nullptr;    // n
@@ -161,6 +169,11 @@ struct MeshDev {
   // grids with them)
   double *curl64 = nullptr;  // n*3*K
   float *curl32 = nullptr;
+  // projected source grids per precision [4 nrhs][V0] (the plane's [4 nrhs]
+  // [Nx Ny] for a planar scatterer): zero once when allocated, after which the
+  // projection writes the occupied nodes only (the same nodes every product)
+  void *src[2] = {nullptr, nullptr};
+  size_t src_bytes[2] = {0, 0};
 };
 
 // milliseconds since an arbitrary epoch (steady clock)

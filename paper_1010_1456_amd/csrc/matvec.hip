@@ -31,11 +31,16 @@ template <typename T>
 constexpr int anterp_epl() {
   return sizeof(T) == 4 ? 2 : 1;
 }
+// With occ (the occupied nodes, increasing) the wave walks npw consecutive
+// occupied nodes instead: node_ptr is then their compacted entry ranges, V0
+// their count, and node i is written at grid index occ[i] of fields of Vg
+// nodes; the other nodes are left untouched (zero in the caller's buffer).
 template <typename T, typename TX>
 __global__ void __launch_bounds__(256)
     k_anterp_gather(const cx<TX> *__restrict__ x, int64_t ldx, int nrhs,
-                    const int32_t *__restrict__ node_ptr, const int32_t *__restrict__ ent_col,
-                    const T *__restrict__ lamT, cx<T> *__restrict__ grid, int64_t V0, int npw) {
+                    const int32_t *__restrict__ node_ptr, const int32_t *__restrict__ occ,
+                    const int32_t *__restrict__ ent_col, const T *__restrict__ lamT,
+                    cx<T> *__restrict__ grid, int64_t V0, int64_t Vg, int npw) {
   constexpr int kEpl = anterp_epl<T>();
   constexpr int C = 64 * kEpl;      // entries per chunk
   __shared__ cx<T> slot[4][C][4];  // [wave][entry][q]
@@ -91,15 +96,22 @@ __global__ void __launch_bounds__(256)
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (ok) {
+      const int64_t node = occ ? (int64_t)occ[v] : v;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         cx<T> o;
         o.x = a[q][0];
         o.y = a[q][1];
-        grid[((int64_t)(r * 4 + q)) * V0 + v] = o;
+        grid[((int64_t)(r * 4 + q)) * Vg + node] = o;
       }
     }
   }
+}
+
+template <typename T>
+__global__ void k_zero(cx<T> *__restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i].x = p[i].y = 0;
 }
 
 // thin [F][Pz][A] grid -> plain [F][A][Pz] (inspection)
@@ -318,6 +330,26 @@ const float2 *tw_of<float>(const MeshDev &md, int d) {
 
 }  // namespace
 
+// the mesh's projected source grid of `bytes` (grown on demand), zero where
+// no projection entry lands
+template <typename T>
+static cx<T> *src_buffer(Plan *pl, MeshDev &md, size_t bytes, hipStream_t s) {
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  if (md.src_bytes[prec] < bytes) {
+    if (md.src[prec]) dev_free(pl, md.src[prec]);
+    md.src[prec] = nullptr;
+    md.src_bytes[prec] = 0;
+    md.src[prec] = dev_alloc(pl, bytes);
+    md.src_bytes[prec] = bytes;
+    ++pl->work_gen;
+    const int64_t n = (int64_t)(bytes / sizeof(cx<T>));
+    hipLaunchKernelGGL((k_zero<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       (cx<T> *)md.src[prec], n);
+    LAUNCHCHECK();
+  }
+  return (cx<T> *)md.src[prec];
+}
+
 void *work_buffer(Plan *pl, int prec, int which, size_t bytes) {
   if (pl->work_bytes[prec][which] < bytes) {
     if (pl->work[prec][which]) dev_free(pl, pl->work[prec][which]);
@@ -351,16 +383,20 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     const int64_t A1 = (int64_t)Nx * Ny, V2 = (int64_t)Nx * Py;
     cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * A1);
     cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2);
+    cx<T> *gs = src_buffer<T>(pl, md, sizeof(cx<T>) * F * A1, s);
     mark(0);
-    hipLaunchKernelGGL((k_anterp_gather<T, TX>),
-                       dim3((unsigned)((A1 + 4 * md.plane_npw - 1) / (4 * md.plane_npw)), nrhs),
-                       dim3(256), 0, s, x, ldx, nrhs, md.plane_node_ptr, md.ent_col,
-                       lamT_of<T>(md), g0, A1, md.plane_npw);
-    LAUNCHCHECK();
+    const int64_t no = md.n_plane_occ;
+    if (no > 0) {
+      hipLaunchKernelGGL((k_anterp_gather<T, TX>),
+                         dim3((unsigned)((no + 4 * md.plane_npw - 1) / (4 * md.plane_npw)), nrhs),
+                         dim3(256), 0, s, x, ldx, nrhs, md.plane_occ_ptr, md.plane_occ,
+                         md.ent_col, lamT_of<T>(md), gs, no, A1, md.plane_npw);
+      LAUNCHCHECK();
+    }
     mark(1);
     if (stop <= 1) return;
     mark(2);
-    fft_pass_contig(g0, g2, md.plan[1], Ny, Py, F * Nx, fftk::contig_map(Ny), fftk::contig_map(Py),
+    fft_pass_contig(gs, g2, md.plan[1], Ny, Py, F * Nx, fftk::contig_map(Ny), fftk::contig_map(Py),
                     false, tw_of<T>(md, 1), s);
     mark(3);
     if (stop <= 3) return;
@@ -382,14 +418,17 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * V0);
     cx<T> *g1 = (cx<T> *)work_buffer(pl, prec, 1, sizeof(cx<T>) * F * V1);
     cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2);
+    cx<T> *gs = src_buffer<T>(pl, md, sizeof(cx<T>) * F * V0, s);
     mark(0);
-    hipLaunchKernelGGL((k_anterp_gather<T, TX>), dim3((unsigned)((V0 + 255) / 256), nrhs),
-                       dim3(256), 0, s, x, ldx, nrhs, md.node_ptr, md.ent_col, lamT_of<T>(md), g0,
-                       V0, 64);
-    LAUNCHCHECK();
+    if (md.n_occ > 0) {
+      hipLaunchKernelGGL((k_anterp_gather<T, TX>), dim3((unsigned)((md.n_occ + 255) / 256), nrhs),
+                         dim3(256), 0, s, x, ldx, nrhs, md.occ_ptr, md.occ, md.ent_col,
+                         lamT_of<T>(md), gs, md.n_occ, V0, 64);
+      LAUNCHCHECK();
+    }
     mark(1);
     if (stop <= 1) return;
-    fft_pass_contig(g0, g1, md.plan[2], Nz, Pz, F * A1, fftk::contig_map(Nz),
+    fft_pass_contig(gs, g1, md.plan[2], Nz, Pz, F * A1, fftk::contig_map(Nz),
                     fftk::contig_map(A1, V1, 1, A1), false, tw_of<T>(md, 2), s);
     mark(2);
     if (stop <= 2) return;
@@ -427,13 +466,16 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
   if (stop <= 1 || !md.fuse_proj[prec] || nrhs > 1 ||
       !anterp_fftz(x, ldx, nrhs, md.node_ptr, md.ent_col, lamT_of<T>(md), Nz, (int64_t)Nx * Ny, g1,
                    Pzs, (int64_t)Nx * Ny * Pzs, tw_of<T>(md, 2), md.plan[2], s)) {
-    hipLaunchKernelGGL((k_anterp_gather<T, TX>), dim3((unsigned)((V0 + 255) / 256), nrhs),
-                       dim3(256), 0, s, x, ldx, nrhs, md.node_ptr, md.ent_col, lamT_of<T>(md), g0,
-                       V0, 64);
-    LAUNCHCHECK();
+    cx<T> *gs = src_buffer<T>(pl, md, sizeof(cx<T>) * F * V0, s);
+    if (md.n_occ > 0) {
+      hipLaunchKernelGGL((k_anterp_gather<T, TX>), dim3((unsigned)((md.n_occ + 255) / 256), nrhs),
+                         dim3(256), 0, s, x, ldx, nrhs, md.occ_ptr, md.occ, md.ent_col,
+                         lamT_of<T>(md), gs, md.n_occ, V0, 64);
+      LAUNCHCHECK();
+    }
     mark(1);
     if (stop <= 1) return;
-    fft_pass_contig(g0, g1, md.plan[2], Nz, Pz, F * Nx * Ny, fftk::contig_map(Nz),
+    fft_pass_contig(gs, g1, md.plan[2], Nz, Pz, F * Nx * Ny, fftk::contig_map(Nz),
                     fftk::contig_map(Pzs), false, tw_of<T>(md, 2), s);
   } else {
     mark(1);
@@ -529,8 +571,9 @@ void copy_far_stage(Plan *pl, MeshDev &md, int nrhs, int stage, void *out, hipSt
                               sizeof(cx<T>) * Pz, (size_t)(F * Nx * Ny), hipMemcpyDeviceToDevice, s));
     return;
   }
-  HIPCHECK(hipMemcpyAsync(out, pl->work[prec][0], sizeof(cx<T>) * F * Nx * Ny * Nz,
-                          hipMemcpyDeviceToDevice, s));
+  // stage 1: the projected source grid; stage 6: the propagated fields
+  HIPCHECK(hipMemcpyAsync(out, stage == 1 ? md.src[prec] : pl->work[prec][0],
+                          sizeof(cx<T>) * F * Nx * Ny * Nz, hipMemcpyDeviceToDevice, s));
 }
 template void copy_far_stage<double>(Plan *, MeshDev &, int, int, void *, hipStream_t);
 template void copy_far_stage<float>(Plan *, MeshDev &, int, int, void *, hipStream_t);

@@ -553,12 +553,38 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
         }
     md.n_entries = ne;
     md.node_ptr = upload(pl, ptr.data(), ptr.size(), s);
+    {
+      std::vector<int32_t> occ, optr;
+      for (int64_t v = 0; v < V0; ++v)
+        if (ptr[v + 1] > ptr[v]) {
+          occ.push_back((int32_t)v);
+          optr.push_back(ptr[v]);
+        }
+      optr.push_back(ptr[V0]);
+      md.n_occ = (int64_t)occ.size();
+      if (occ.empty()) occ.push_back(0);
+      md.occ = upload(pl, occ.data(), occ.size(), s);
+      md.occ_ptr = upload(pl, optr.data(), optr.size(), s);
+      HIPCHECK(hipStreamSynchronize(s));  // host vectors go out of scope
+    }
     if (md.planar_z >= 0) {  // all entries sit on the plane: plane node p = x Ny + y
       const int64_t A = (int64_t)h.grid[0] * h.grid[1];
       std::vector<int32_t> p2(A + 1);
       for (int64_t p = 0; p < A; ++p) p2[p] = ptr[p * h.grid[2] + md.planar_z];
       p2[A] = ptr[V0];
       md.plane_node_ptr = upload(pl, p2.data(), p2.size(), s);
+      std::vector<int32_t> occ, optr;
+      for (int64_t p = 0; p < A; ++p)
+        if (p2[p + 1] > p2[p]) {
+          occ.push_back((int32_t)p);
+          optr.push_back(p2[p]);
+        }
+      optr.push_back(p2[A]);
+      md.n_plane_occ = (int64_t)occ.size();
+      if (occ.empty()) occ.push_back(0);
+      md.plane_occ = upload(pl, occ.data(), occ.size(), s);
+      md.plane_occ_ptr = upload(pl, optr.data(), optr.size(), s);
+      HIPCHECK(hipStreamSynchronize(s));  // host vectors go out of scope
     }
     md.ent_col = upload(pl, col.data(), col.size(), s);
     int32_t *dsrc = upload(pl, src.data(), src.size(), s);
