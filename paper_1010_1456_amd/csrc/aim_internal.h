@@ -137,6 +137,11 @@ struct MeshDev {
   int64_t n_occ = 0;
   int32_t *occ = nullptr;      // n_occ node indices, increasing
   int32_t *occ_ptr = nullptr;  // n_occ + 1
+  // the z lines (x Ny + y) holding an occupied node: the interpolation reads
+  // the propagated fields on these lines only, so the inverse z pass skips
+  // the others
+  int64_t n_occ_lines = 0;
+  int32_t *occ_lines = nullptr;
   int32_t *ent_col = nullptr;   // n_entries
   double *lamT64 = nullptr;     // n_entries * 4
   float *lamT32 = nullptr;      // n_entries * 4
@@ -253,7 +258,7 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
 template <typename T, typename TX, typename TY>
 void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, cx<TY> *y,
                  int64_t ldy, hipStream_t s, hipEvent_t *ev = nullptr);
-void *work_buffer(Plan *pl, int prec, int which, size_t bytes);
+void *work_buffer(Plan *pl, int prec, int which, size_t bytes, hipStream_t s);
 // copies the grid buffer after far stage `stage` to out in plain layout
 template <typename T>
 void copy_far_stage(Plan *pl, MeshDev &md, int nrhs, int stage, void *out, hipStream_t s);

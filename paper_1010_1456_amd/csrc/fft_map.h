@@ -54,10 +54,19 @@ inline LineMap blocked_map(int64_t field_stride, int Nx, int Py, int blk) {
 
 // Line addressing of the contiguous passes: line L = f per + l starts at
 // f fs + l ls (per = 0: no split, L ls), its elements es apart.
+// With sel, a pass runs only the selected lines of each field: pass line L is
+// line (L / nsel) sper + sel[L % nsel] of the full numbering (sper lines per
+// field), which the map then addresses (device side only).
 struct ContigMap {
   int64_t per, fs, ls, es;
+  const int32_t *sel = nullptr;
+  int64_t nsel = 0, sper = 0;
 };
 __host__ __device__ inline int64_t contig_base(const ContigMap &m, int64_t L) {
+  if (m.sel) {
+    const int64_t f = L / m.nsel;
+    L = f * m.sper + m.sel[L - f * m.nsel];
+  }
   if (m.per == 0) return L * m.ls;
   const int64_t f = L / m.per;
   return f * m.fs + (L - f * m.per) * m.ls;
@@ -67,6 +76,13 @@ inline ContigMap contig_map(int64_t ls) { return ContigMap{0, 0, ls, 1}; }
 // per lines of each of the fields fs apart, lines ls apart, elements es apart
 inline ContigMap contig_map(int64_t per, int64_t fs, int64_t ls, int64_t es) {
   return ContigMap{per, fs, ls, es};
+}
+// the same map over the selected lines sel[0 .. nsel) of each field of sper lines
+inline ContigMap select_lines(ContigMap m, const int32_t *sel, int64_t nsel, int64_t sper) {
+  m.sel = sel;
+  m.nsel = nsel;
+  m.sper = sper;
+  return m;
 }
 
 }  // namespace fftk

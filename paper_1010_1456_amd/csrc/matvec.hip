@@ -350,7 +350,7 @@ static cx<T> *src_buffer(Plan *pl, MeshDev &md, size_t bytes, hipStream_t s) {
   return (cx<T> *)md.src[prec];
 }
 
-void *work_buffer(Plan *pl, int prec, int which, size_t bytes) {
+void *work_buffer(Plan *pl, int prec, int which, size_t bytes, hipStream_t s) {
   if (pl->work_bytes[prec][which] < bytes) {
     if (pl->work[prec][which]) dev_free(pl, pl->work[prec][which]);
     pl->work[prec][which] = nullptr;
@@ -358,6 +358,21 @@ void *work_buffer(Plan *pl, int prec, int which, size_t bytes) {
     pl->work[prec][which] = dev_alloc(pl, bytes);
     pl->work_bytes[prec][which] = bytes;
     ++pl->work_gen;
+    if (which == 0) {
+      // the propagated fields: the inverse z pass writes the occupied lines
+      // only and the interpolation multiplies the others by zero weights, so
+      // they must hold finite values
+      if (prec == 0) {
+        const int64_t n = (int64_t)(bytes / sizeof(double2));
+        hipLaunchKernelGGL((k_zero<double>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           (double2 *)pl->work[prec][which], n);
+      } else {
+        const int64_t n = (int64_t)(bytes / sizeof(float2));
+        hipLaunchKernelGGL((k_zero<float>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           (float2 *)pl->work[prec][which], n);
+      }
+      LAUNCHCHECK();
+    }
   }
   return pl->work[prec][which];
 }
@@ -381,8 +396,8 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     // the interpolation: the plane alone, g0 = [F][Nx][Ny], 2-D propagation
     // (y passes, x pass with the 2-D spectrum)
     const int64_t A1 = (int64_t)Nx * Ny, V2 = (int64_t)Nx * Py;
-    cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * A1);
-    cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2);
+    cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * A1, s);
+    cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2, s);
     cx<T> *gs = src_buffer<T>(pl, md, sizeof(cx<T>) * F * A1, s);
     mark(0);
     const int64_t no = md.n_plane_occ;
@@ -415,9 +430,9 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     // g2 [F][Pz][Nx][Py], no row padding; the y lines are contiguous, the x
     // pass tiles consecutive ky
     const int64_t A1 = (int64_t)Nx * Ny, V1 = Pz * A1, V2 = (int64_t)Pz * Nx * Py;
-    cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * V0);
-    cx<T> *g1 = (cx<T> *)work_buffer(pl, prec, 1, sizeof(cx<T>) * F * V1);
-    cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2);
+    cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * V0, s);
+    cx<T> *g1 = (cx<T> *)work_buffer(pl, prec, 1, sizeof(cx<T>) * F * V1, s);
+    cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2, s);
     cx<T> *gs = src_buffer<T>(pl, md, sizeof(cx<T>) * F * V0, s);
     mark(0);
     if (md.n_occ > 0) {
@@ -444,17 +459,25 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
                     fftk::contig_map(Ny), true, tw_of<T>(md, 1), s);
     mark(5);
     if (stop <= 5) return;
-    fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * A1, fftk::contig_map(A1, V1, 1, A1),
-                    fftk::contig_map(Nz), true, tw_of<T>(md, 2), s);
+    if (full3d) {  // inspection: every line
+      fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * A1, fftk::contig_map(A1, V1, 1, A1),
+                      fftk::contig_map(Nz), true, tw_of<T>(md, 2), s);
+    } else {  // the lines the interpolation reads
+      const int64_t nl = md.n_occ_lines;
+      fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * nl,
+                      fftk::select_lines(fftk::contig_map(A1, V1, 1, A1), md.occ_lines, nl, A1),
+                      fftk::select_lines(fftk::contig_map(Nz), md.occ_lines, nl, A1), true,
+                      tw_of<T>(md, 2), s);
+    }
     mark(6);
     return;
   }
   const int Pzs = (Pz + blk - 1) / blk * blk;  // z rows padded to 128-byte multiples
   const int64_t V1 = (int64_t)Nx * Ny * Pzs;
   const int64_t V2 = (int64_t)Nx * Py * ((Pz + blk - 1) / blk * blk);  // kz-blocked
-  cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * V0);
-  cx<T> *g1 = (cx<T> *)work_buffer(pl, prec, 1, sizeof(cx<T>) * F * V1);
-  cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2);
+  cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * V0, s);
+  cx<T> *g1 = (cx<T> *)work_buffer(pl, prec, 1, sizeof(cx<T>) * F * V1, s);
+  cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2, s);
   const fftk::LineMap m1 = fftk::plain_map((int64_t)Ny * Pzs, Pzs);
   const fftk::LineMap m2 = fftk::blocked_map(V2, Nx, Py, blk);
   mark(0);
@@ -492,8 +515,16 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
   fft_pass_strided(g2, g1, md.plan[1], Py, Ny, F * Nx, Pz, m2, m1, true, tw_of<T>(md, 1), s);
   mark(5);
   if (stop <= 5) return;
-  fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * Nx * Ny, fftk::contig_map(Pzs),
-                  fftk::contig_map(Nz), true, tw_of<T>(md, 2), s);
+  if (full3d) {  // inspection: every line
+    fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * Nx * Ny, fftk::contig_map(Pzs),
+                    fftk::contig_map(Nz), true, tw_of<T>(md, 2), s);
+  } else {  // the lines the interpolation reads
+    const int64_t nl = md.n_occ_lines, A1 = (int64_t)Nx * Ny;
+    fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * nl,
+                    fftk::select_lines(fftk::contig_map(Pzs), md.occ_lines, nl, A1),
+                    fftk::select_lines(fftk::contig_map(Nz), md.occ_lines, nl, A1), true,
+                    tw_of<T>(md, 2), s);
+  }
   mark(6);
 }
 

@@ -561,10 +561,16 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
           optr.push_back(ptr[v]);
         }
       optr.push_back(ptr[V0]);
+      std::vector<int32_t> lines;
+      for (int32_t v : occ)
+        if (lines.empty() || lines.back() != v / h.grid[2]) lines.push_back(v / h.grid[2]);
       md.n_occ = (int64_t)occ.size();
+      md.n_occ_lines = (int64_t)lines.size();
       if (occ.empty()) occ.push_back(0);
+      if (lines.empty()) lines.push_back(0);
       md.occ = upload(pl, occ.data(), occ.size(), s);
       md.occ_ptr = upload(pl, optr.data(), optr.size(), s);
+      md.occ_lines = upload(pl, lines.data(), lines.size(), s);
       HIPCHECK(hipStreamSynchronize(s));  // host vectors go out of scope
     }
     if (md.planar_z >= 0) {  // all entries sit on the plane: plane node p = x Ny + y
