@@ -179,6 +179,11 @@ struct MeshDev {
   // projection writes the occupied nodes only (the same nodes every product)
   void *src[2] = {nullptr, nullptr};
   size_t src_bytes[2] = {0, 0};
+  // forward z transforms of those grids per precision [4 nrhs][Nx Ny][Pzs]
+  // (kz-blocked grids only): zero once, after which the forward z pass
+  // writes the occupied z lines only
+  void *fz[2] = {nullptr, nullptr};
+  size_t fz_bytes[2] = {0, 0};
 };
 
 // milliseconds since an arbitrary epoch (steady clock)

@@ -330,24 +330,30 @@ const float2 *tw_of<float>(const MeshDev &md, int d) {
 
 }  // namespace
 
-// the mesh's projected source grid of `bytes` (grown on demand), zero where
-// no projection entry lands
+// a per-mesh grid buffer of `bytes` (grown on demand) that is zero wherever
+// the kernels writing it never write
 template <typename T>
-static cx<T> *src_buffer(Plan *pl, MeshDev &md, size_t bytes, hipStream_t s) {
+static cx<T> *zeroed_buffer(Plan *pl, void *(&buf)[2], size_t (&have)[2], size_t bytes,
+                            hipStream_t s) {
   const int prec = sizeof(T) == 8 ? 0 : 1;
-  if (md.src_bytes[prec] < bytes) {
-    if (md.src[prec]) dev_free(pl, md.src[prec]);
-    md.src[prec] = nullptr;
-    md.src_bytes[prec] = 0;
-    md.src[prec] = dev_alloc(pl, bytes);
-    md.src_bytes[prec] = bytes;
+  if (have[prec] < bytes) {
+    if (buf[prec]) dev_free(pl, buf[prec]);
+    buf[prec] = nullptr;
+    have[prec] = 0;
+    buf[prec] = dev_alloc(pl, bytes);
+    have[prec] = bytes;
     ++pl->work_gen;
     const int64_t n = (int64_t)(bytes / sizeof(cx<T>));
     hipLaunchKernelGGL((k_zero<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                       (cx<T> *)md.src[prec], n);
+                       (cx<T> *)buf[prec], n);
     LAUNCHCHECK();
   }
-  return (cx<T> *)md.src[prec];
+  return (cx<T> *)buf[prec];
+}
+// the mesh's projected source grid, zero where no projection entry lands
+template <typename T>
+static cx<T> *src_buffer(Plan *pl, MeshDev &md, size_t bytes, hipStream_t s) {
+  return zeroed_buffer<T>(pl, md.src, md.src_bytes, bytes, s);
 }
 
 void *work_buffer(Plan *pl, int prec, int which, size_t bytes, hipStream_t s) {
@@ -480,6 +486,7 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
   cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2, s);
   const fftk::LineMap m1 = fftk::plain_map((int64_t)Ny * Pzs, Pzs);
   const fftk::LineMap m2 = fftk::blocked_map(V2, Nx, Py, blk);
+  cx<T> *gz = g1;  // forward z output, forward y input
   mark(0);
   // projection fused with the forward z pass: the projected grid is never
   // stored (except for inspection, or for FFT lengths without a fused kernel).
@@ -498,14 +505,23 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     }
     mark(1);
     if (stop <= 1) return;
-    fft_pass_contig(gs, g1, md.plan[2], Nz, Pz, F * Nx * Ny, fftk::contig_map(Nz),
-                    fftk::contig_map(Pzs), false, tw_of<T>(md, 2), s);
+    if (full3d) {  // inspection: every line, into g1
+      fft_pass_contig(gs, g1, md.plan[2], Nz, Pz, F * Nx * Ny, fftk::contig_map(Nz),
+                      fftk::contig_map(Pzs), false, tw_of<T>(md, 2), s);
+    } else {  // the occupied lines into the mesh's zeroed buffer (the others stay zero)
+      const int64_t nl = md.n_occ_lines, A1 = (int64_t)Nx * Ny;
+      gz = zeroed_buffer<T>(pl, md.fz, md.fz_bytes, sizeof(cx<T>) * F * V1, s);
+      fft_pass_contig(gs, gz, md.plan[2], Nz, Pz, F * nl,
+                      fftk::select_lines(fftk::contig_map(Nz), md.occ_lines, nl, A1),
+                      fftk::select_lines(fftk::contig_map(Pzs), md.occ_lines, nl, A1), false,
+                      tw_of<T>(md, 2), s);
+    }
   } else {
     mark(1);
   }
   mark(2);
   if (stop <= 2) return;
-  fft_pass_strided(g1, g2, md.plan[1], Ny, Py, F * Nx, Pz, m1, m2, false, tw_of<T>(md, 1), s);
+  fft_pass_strided(gz, g2, md.plan[1], Ny, Py, F * Nx, Pz, m1, m2, false, tw_of<T>(md, 1), s);
   mark(3);
   if (stop <= 3) return;
   fft_mid_pass(g2, md.plan[0], Nx, (int)F, Py, Pz, md.H[0], md.H[1], md.H[2], ghat_of<T>(md),
