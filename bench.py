@@ -135,13 +135,17 @@ def measured_traffic(workload, kernel_prefix):
 
 def stage_bytes(info, mesh, nrhs, s_grid, s_real, s_x, s_y, path):
     """Algorithmic HBM bytes of each step of one product: every operator datum
-    read once, vectors read/written once, grid fields per the pruned passes."""
+    read once, vectors read/written once, grid fields per the pruned passes:
+    the projection writes and the interpolation reads the occupied nodes only
+    (O of them, on L z lines), the z passes move the L occupied lines, the
+    forward y pass reads their rows and the inverse y pass writes them."""
     n = info["n"][mesh]
     nnz = info["nnz"][mesh]
     K = (info["order"] + 1) ** 3
     Nx, Ny, Nz = info["grid"][mesh]
     Px, Py, Pz = info["pad"][mesh]
-    V0, V1, V2 = Nx * Ny * Nz, Nx * Ny * Pz, Nx * Py * Pz
+    V2 = Nx * Py * Pz
+    O, L = info["occ_nodes"][mesh], info["occ_lines"][mesh]
     F = 4 * nrhs
     H = (Px // 2 + 1) * (Py // 2 + 1) * (Pz // 2 + 1)
     lam = n * (4 * K * s_real + 4)
@@ -151,26 +155,26 @@ def stage_bytes(info, mesh, nrhs, s_grid, s_real, s_x, s_y, path):
         H2 = (Px // 2 + 1) * (Py // 2 + 1)
         lam2 = n * (4 * (info["order"] + 1) ** 2 * s_real + 4)
         return np.array([
-            F * A1 * s_grid + lam2 + nrhs * n * s_x,
+            F * O * s_grid + lam2 + nrhs * n * s_x,
             0.0,
             F * (A1 + A2) * s_grid,
             2 * F * A2 * s_grid + H2 * s_grid,
             F * (A2 + A1) * s_grid,
             0.0,
-            F * A1 * s_grid + lam2 + nnz * (s_grid + 4) + 4 * (n + 1) + nrhs * n * (s_x + s_y),
+            F * O * s_grid + lam2 + nnz * (s_grid + 4) + 4 * (n + 1) + nrhs * n * (s_x + s_y),
         ], dtype=np.float64)
     if info["fused_projection"][mesh][path]:  # projection inside the forward z pass
-        proj, fwdz = lam + nrhs * n * s_x + F * V1 * s_grid, 0.0
+        proj, fwdz = lam + nrhs * n * s_x + F * L * Pz * s_grid, 0.0
     else:
-        proj, fwdz = F * V0 * s_grid + lam + nrhs * n * s_x, F * (V0 + V1) * s_grid
+        proj, fwdz = F * O * s_grid + lam + nrhs * n * s_x, F * L * (Nz + Pz) * s_grid
     return np.array([
         proj,                                                          # projection (+ forward z)
         fwdz,                                                          # forward z
-        F * (V1 + V2) * s_grid,                                        # forward y
+        F * (L * Pz + V2) * s_grid,                                    # forward y
         2 * F * V2 * s_grid + H * s_grid,                              # x pass + spectrum
-        F * (V2 + V1) * s_grid,                                        # inverse y
-        F * (V1 + V0) * s_grid,                                        # inverse z
-        F * V0 * s_grid + lam + nnz * (s_grid + 4) + 4 * (n + 1)
+        F * (V2 + L * Pz) * s_grid,                                    # inverse y
+        F * L * (Pz + Nz) * s_grid,                                    # inverse z
+        F * O * s_grid + lam + nnz * (s_grid + 4) + 4 * (n + 1)
         + nrhs * n * (s_x + s_y) + curl,                               # interp + near
     ], dtype=np.float64)
 

@@ -178,6 +178,11 @@ typedef struct {
                                                the matrix fill) */
   double cfie_alpha[AIM_MAX_MESH];      /* combined-field parameter of each mesh, or -1 where
                                            the mesh uses the EFIE */
+  int64_t occ_nodes[AIM_MAX_MESH];      /* grid nodes with a non-zero projection weight (the
+                                           only nodes the projection writes and the
+                                           interpolation reads; plane nodes for planar_z >= 0) */
+  int64_t occ_lines[AIM_MAX_MESH];      /* z lines (x, y) holding such a node (the only lines
+                                           the z passes transform) */
 } aim_info;
 
 /* GMRES options. restart m (<= 200), relative-residual tolerance on

@@ -231,6 +231,8 @@ aim_status aim_plan_info(const aim_plan *plan, aim_info *out) {
     out->fused_projection[i][1] = md.fuse_proj[1];
     out->planar_z[i] = md.planar_z;
     out->cfie_alpha[i] = md.hp.cfie ? md.hp.alpha : -1.0;
+    out->occ_nodes[i] = md.planar_z >= 0 ? md.n_plane_occ : md.n_occ;
+    out->occ_lines[i] = md.n_occ_lines;
     for (int j = 0; j < AIM_NSETUP; ++j) out->setup_ms[i][j] = md.setup_ms[j];
   }
   out->device_bytes = plan->device_bytes;
