@@ -142,6 +142,9 @@ struct MeshDev {
   // the others
   int64_t n_occ_lines = 0;
   int32_t *occ_lines = nullptr;
+  // per x: the y range [lo, hi) of the occupied z lines (x, y); the y passes
+  // read (forward) and write (inverse) only these rows
+  int32_t *occ_yrange = nullptr;  // 2 Nx
   int32_t *ent_col = nullptr;   // n_entries
   double *lamT64 = nullptr;     // n_entries * 4
   float *lamT32 = nullptr;      // n_entries * 4

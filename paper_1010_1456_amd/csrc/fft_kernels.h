@@ -189,6 +189,18 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
   const int in_elem = (int)line_elem(imap), out_elem = (int)line_elem(omap);
   const V *gin_b = gin + beta * in_elem;
   V *gout_b = gout + beta * out_elem;
+  // element ranges of this line (all of it without a range table)
+  int in_lo = 0, in_hi = n_in, out_lo = 0, out_hi = n_out;
+  if (imap.range) {
+    const int r = (int)(o % imap.range_rows);
+    in_lo = imap.range[2 * r];
+    in_hi = min(n_in, imap.range[2 * r + 1]);
+  }
+  if (omap.range) {
+    const int r = (int)(o % omap.range_rows);
+    out_lo = omap.range[2 * r];
+    out_hi = min(n_out, omap.range[2 * r + 1]);
+  }
   V *twl = lds + (PC::ns > 1 ? P * B : 0);
   if constexpr (PC::ns > 1) {
     for (int i = threadIdx.x; i < P; i += blockDim.x) twl[i] = tw[i];
@@ -200,12 +212,13 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
     constexpr bool first = (s == 0), last = (s == PC::ns - 1);
     const bool active = line_ok && (beta < nb);
     auto ld = [&](int i) AIM_AI -> V {
-      if constexpr (first) return (i < n_in) ? gin_b[(i - beta) * in_elem] : mk<V>((T)0, (T)0);
+      if constexpr (first)
+        return (i >= in_lo && i < in_hi) ? gin_b[(i - beta) * in_elem] : mk<V>((T)0, (T)0);
       else return lds[i * B + b];
     };
     auto st = [&](int i, V v) AIM_AI {
       if constexpr (last) {
-        if (i < n_out) gout_b[(i - beta) * out_elem] = v;
+        if (i >= out_lo && i < out_hi) gout_b[(i - beta) * out_elem] = v;
       } else {
         lds[i * B + b] = v;
       }

@@ -18,7 +18,17 @@ namespace fftk {
 struct LineMap {
   int64_t hi, lo, bstr, elem;
   int lo_count, blk;
+  // optional element range per line: a line with outer index o holds
+  // elements range[2 r] <= i < range[2 r + 1] only, r = o % range_rows (the
+  // others read as zero on input and are not stored on output)
+  const int32_t *range = nullptr;
+  int range_rows = 0;
 };
+inline LineMap with_range(LineMap m, const int32_t *range, int rows) {
+  m.range = range;
+  m.range_rows = rows;
+  return m;
+}
 __host__ __device__ inline int64_t line_base(const LineMap &m, int64_t o, int64_t c) {
   const int64_t oh = o / m.lo_count, ol = o - oh * m.lo_count;
   const int64_t b = oh * m.hi + ol * m.lo;

@@ -521,14 +521,17 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
   }
   mark(2);
   if (stop <= 2) return;
-  fft_pass_strided(gz, g2, md.plan[1], Ny, Py, F * Nx, Pz, m1, m2, false, tw_of<T>(md, 1), s);
+  // y passes: rows outside a plane's occupied y range are zero on input
+  // (forward) and never read on output (inverse); inspection keeps every row
+  const fftk::LineMap m1y = full3d ? m1 : fftk::with_range(m1, md.occ_yrange, Nx);
+  fft_pass_strided(gz, g2, md.plan[1], Ny, Py, F * Nx, Pz, m1y, m2, false, tw_of<T>(md, 1), s);
   mark(3);
   if (stop <= 3) return;
   fft_mid_pass(g2, md.plan[0], Nx, (int)F, Py, Pz, md.H[0], md.H[1], md.H[2], ghat_of<T>(md),
                tw_of<T>(md, 0), blk, V2, s);
   mark(4);
   if (stop <= 4) return;
-  fft_pass_strided(g2, g1, md.plan[1], Py, Ny, F * Nx, Pz, m2, m1, true, tw_of<T>(md, 1), s);
+  fft_pass_strided(g2, g1, md.plan[1], Py, Ny, F * Nx, Pz, m2, m1y, true, tw_of<T>(md, 1), s);
   mark(5);
   if (stop <= 5) return;
   if (full3d) {  // inspection: every line

@@ -571,6 +571,16 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
       md.occ = upload(pl, occ.data(), occ.size(), s);
       md.occ_ptr = upload(pl, optr.data(), optr.size(), s);
       md.occ_lines = upload(pl, lines.data(), lines.size(), s);
+      std::vector<int32_t> yr(2 * (size_t)h.grid[0], 0);
+      for (int64_t x = 0; x < h.grid[0]; ++x) yr[2 * x] = h.grid[1];
+      for (int64_t i = 0; i < md.n_occ_lines; ++i) {
+        const int64_t x = lines[i] / h.grid[1], y = lines[i] % h.grid[1];
+        yr[2 * x] = std::min<int32_t>(yr[2 * x], (int32_t)y);
+        yr[2 * x + 1] = std::max<int32_t>(yr[2 * x + 1], (int32_t)y + 1);
+      }
+      for (int64_t x = 0; x < h.grid[0]; ++x)
+        if (yr[2 * x] > yr[2 * x + 1]) yr[2 * x] = yr[2 * x + 1] = 0;
+      md.occ_yrange = upload(pl, yr.data(), yr.size(), s);
       HIPCHECK(hipStreamSynchronize(s));  // host vectors go out of scope
     }
     if (md.planar_z >= 0) {  // all entries sit on the plane: plane node p = x Ny + y
