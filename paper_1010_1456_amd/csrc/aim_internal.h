@@ -145,6 +145,9 @@ struct MeshDev {
   // per x: the y range [lo, hi) of the occupied z lines (x, y); the y passes
   // read (forward) and write (inverse) only these rows
   int32_t *occ_yrange = nullptr;  // 2 Nx
+  // per occupied z line: the z range [lo, hi) of its occupied nodes (the z
+  // passes read and write only these elements of the grid side)
+  int32_t *occ_zrange = nullptr;  // 2 n_occ_lines
   int32_t *ent_col = nullptr;   // n_entries
   double *lamT64 = nullptr;     // n_entries * 4
   float *lamT32 = nullptr;      // n_entries * 4

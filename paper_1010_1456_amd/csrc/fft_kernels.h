@@ -142,13 +142,25 @@ __global__ void __launch_bounds__((threads_contig<T, PC>()))
     V *gout = out + contig_base(omap, line0 + b);
     V *ll = lds + b * LS;
     (void)tw;
+    int in_lo = 0, in_hi = n_in, out_lo = 0, out_hi = n_out;
+    if (first && imap.range) {
+      const int64_t r = (line0 + b) % imap.nsel;
+      in_lo = imap.range[2 * r];
+      in_hi = min(n_in, imap.range[2 * r + 1]);
+    }
+    if (last && omap.range) {
+      const int64_t r = (line0 + b) % omap.nsel;
+      out_lo = omap.range[2 * r];
+      out_hi = min(n_out, omap.range[2 * r + 1]);
+    }
     auto ld = [&](int i) AIM_AI -> V {
-      if constexpr (first) return (i < n_in) ? gin[i * imap.es] : mk<V>((T)0, (T)0);
+      if constexpr (first)
+        return (i >= in_lo && i < in_hi) ? gin[i * imap.es] : mk<V>((T)0, (T)0);
       else return ll[i];
     };
     auto st = [&](int i, V v) AIM_AI {
       if constexpr (last) {
-        if (i < n_out) gout[i * omap.es] = v;
+        if (i >= out_lo && i < out_hi) gout[i * omap.es] = v;
       } else {
         ll[i] = v;
       }

@@ -71,6 +71,10 @@ struct ContigMap {
   int64_t per, fs, ls, es;
   const int32_t *sel = nullptr;
   int64_t nsel = 0, sper = 0;
+  // optional element range of each selected line s = L % nsel: elements
+  // range[2 s] <= i < range[2 s + 1] only (the others read as zero on input,
+  // are not stored on output)
+  const int32_t *range = nullptr;
 };
 __host__ __device__ inline int64_t contig_base(const ContigMap &m, int64_t L) {
   if (m.sel) {
@@ -88,10 +92,12 @@ inline ContigMap contig_map(int64_t per, int64_t fs, int64_t ls, int64_t es) {
   return ContigMap{per, fs, ls, es};
 }
 // the same map over the selected lines sel[0 .. nsel) of each field of sper lines
-inline ContigMap select_lines(ContigMap m, const int32_t *sel, int64_t nsel, int64_t sper) {
+inline ContigMap select_lines(ContigMap m, const int32_t *sel, int64_t nsel, int64_t sper,
+                              const int32_t *range = nullptr) {
   m.sel = sel;
   m.nsel = nsel;
   m.sper = sper;
+  m.range = range;
   return m;
 }
 

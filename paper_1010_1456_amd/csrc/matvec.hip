@@ -512,7 +512,7 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
       const int64_t nl = md.n_occ_lines, A1 = (int64_t)Nx * Ny;
       gz = zeroed_buffer<T>(pl, md.fz, md.fz_bytes, sizeof(cx<T>) * F * V1, s);
       fft_pass_contig(gs, gz, md.plan[2], Nz, Pz, F * nl,
-                      fftk::select_lines(fftk::contig_map(Nz), md.occ_lines, nl, A1),
+                      fftk::select_lines(fftk::contig_map(Nz), md.occ_lines, nl, A1, md.occ_zrange),
                       fftk::select_lines(fftk::contig_map(Pzs), md.occ_lines, nl, A1), false,
                       tw_of<T>(md, 2), s);
     }
@@ -541,8 +541,8 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     const int64_t nl = md.n_occ_lines, A1 = (int64_t)Nx * Ny;
     fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * nl,
                     fftk::select_lines(fftk::contig_map(Pzs), md.occ_lines, nl, A1),
-                    fftk::select_lines(fftk::contig_map(Nz), md.occ_lines, nl, A1), true,
-                    tw_of<T>(md, 2), s);
+                    fftk::select_lines(fftk::contig_map(Nz), md.occ_lines, nl, A1, md.occ_zrange),
+                    true, tw_of<T>(md, 2), s);
   }
   mark(6);
 }

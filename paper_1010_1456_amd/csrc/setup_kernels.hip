@@ -122,14 +122,20 @@ __global__ void k_curl_projection(const int32_t *rwg, const double *len, const d
   curl[(b * 3 + 2) * K + u] = acc.z;
 }
 
-// 1 where a (basis, stencil node) pair has any non-zero weight
-__global__ void k_lam_mask(const double *lam, int64_t n, int K, uint8_t *mask) {
+// 1 where a (basis, stencil node) pair has any non-zero weight: projection
+// or, for the combined field, curl weight (the node is then read by the
+// interpolation even where its projection weights vanish, as off a flat face
+// lying in a grid plane)
+__global__ void k_lam_mask(const double *lam, const double *curl, int64_t n, int K,
+                           uint8_t *mask) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * K) return;
   const int64_t b = t / K;
   const int u = (int)(t - b * K);
   bool nz = false;
   for (int q = 0; q < 4; ++q) nz |= lam[(b * 4 + q) * K + u] != 0.0;
+  if (curl)
+    for (int e = 0; e < 3; ++e) nz |= curl[(b * 3 + e) * K + u] != 0.0;
   mask[t] = nz ? 1 : 0;
 }
 
@@ -528,7 +534,8 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
   {
     const int64_t NK = n * K;
     uint8_t *dmask = (uint8_t *)dev_alloc(pl, NK);
-    hipLaunchKernelGGL(k_lam_mask, dim3(blocks_for(NK, 256)), dim3(256), 0, s, md.lam64, n, K, dmask);
+    hipLaunchKernelGGL(k_lam_mask, dim3(blocks_for(NK, 256)), dim3(256), 0, s, md.lam64, md.curl64,
+                       n, K, dmask);
     LAUNCHCHECK();
     std::vector<uint8_t> mask(NK);
     HIPCHECK(hipMemcpyAsync(mask.data(), dmask, NK, hipMemcpyDeviceToHost, s));
@@ -581,6 +588,18 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
       for (int64_t x = 0; x < h.grid[0]; ++x)
         if (yr[2 * x] > yr[2 * x + 1]) yr[2 * x] = yr[2 * x + 1] = 0;
       md.occ_yrange = upload(pl, yr.data(), yr.size(), s);
+      std::vector<int32_t> zr;  // occupied nodes are increasing, so lines come in order
+      for (int64_t i = 0; i < md.n_occ; ++i) {
+        const int32_t line = occ[i] / h.grid[2], z = occ[i] % h.grid[2];
+        if (zr.empty() || line != occ[i - 1] / h.grid[2]) {
+          zr.push_back(z);
+          zr.push_back(z + 1);
+        } else {
+          zr.back() = z + 1;
+        }
+      }
+      if (zr.empty()) zr.assign(2, 0);
+      md.occ_zrange = upload(pl, zr.data(), zr.size(), s);
       HIPCHECK(hipStreamSynchronize(s));  // host vectors go out of scope
     }
     if (md.planar_z >= 0) {  // all entries sit on the plane: plane node p = x Ny + y
