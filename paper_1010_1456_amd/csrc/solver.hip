@@ -161,6 +161,38 @@ __global__ void k_normalize(const double2 *w, double2 *out, int64_t ld, int64_t 
   out[(int64_t)r * ld + n] = make_double2(p.x * inv, p.y * inv);
 }
 
+// The end of an Arnoldi step in one launch: the squared norm of w from the
+// k_norm2_part partials (every work-group adds them in the order of
+// k_norm_reduce; work-group 0 stores it for the Givens kernel), v_{j+1} =
+// w / |w| into out, and the next step's preconditioned vector
+// z = dinv v_{j+1} (what k_precond would compute from out).
+__global__ void __launch_bounds__(256)
+    k_normalize_next(const double2 *w, double2 *out, double2 *z, const double2 *dinv, int64_t ld,
+                     int64_t lo, int64_t hi, int sys0, const double *part, int np, double *nrm) {
+  __shared__ double snrm;
+  const int r = blockIdx.y;
+  const int s = sys0 + r;
+  if (threadIdx.x < 64) {
+    double a = 0;
+    for (int q = threadIdx.x; q < np; q += 64) a += part[(int64_t)s * kNormParts + q];
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if (threadIdx.x == 0) {
+      snrm = a;
+      if (blockIdx.x == 0) nrm[s] = a;
+    }
+  }
+  __syncthreads();
+  const int64_t n = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= hi) return;
+  const double sv = snrm;
+  const double inv = sv > 0 ? 1.0 / sqrt(sv) : 0.0;
+  const double2 p = w[(int64_t)r * ld + n];
+  const double2 v = make_double2(p.x * inv, p.y * inv);
+  out[(int64_t)r * ld + n] = v;
+  const double2 d = dinv[n];
+  z[(int64_t)r * ld + n] = make_double2(v.x * d.x - v.y * d.y, v.x * d.y + v.y * d.x);
+}
+
 // z[r][row] = v[r][row] / d[row]
 __global__ void k_precond(const double2 *v, double2 *z, const double2 *dinv, int64_t ld, int R) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -469,9 +501,11 @@ SolverState &solver_state(Plan *pl, int R, int m) {
 void arnoldi_step(Ctx &c, aim_precision prec, Work &wk, int j, int m) {
   const int S = c.S, R = c.R;
   const int64_t ld = c.ld, vstride = (int64_t)R * ld;
-  hipLaunchKernelGGL(k_precond, dim3(nblk(ld, 256)), dim3(256), 0, c.s, wk.V + j * vstride, wk.z,
-                     c.dinv, ld, R);
-  LAUNCHCHECK();
+  if (j == 0) {  // later steps find z = dinv v_j left by the previous step
+    hipLaunchKernelGGL(k_precond, dim3(nblk(ld, 256)), dim3(256), 0, c.s, wk.V + j * vstride, wk.z,
+                       c.dinv, ld, R);
+    LAUNCHCHECK();
+  }
   apply(c, prec, wk.z, wk.w);
   for (int pass = 0; pass < 2; ++pass) {
     double2 *h = pass == 0 ? wk.h1 : wk.h2;
@@ -491,12 +525,15 @@ void arnoldi_step(Ctx &c, aim_precision prec, Work &wk, int j, int m) {
       ++mi;
     }
   }
-  norms_dev(c, wk.w, wk.npart, wk.nrm);
   int mi = 0;
   for (auto &md : c.pl->mesh) {
-    hipLaunchKernelGGL(k_normalize, dim3(nblk(md.hp.n, 256), R), dim3(256), 0, c.s, wk.w,
-                       wk.V + (j + 1) * vstride, ld, md.offset, md.offset + md.hp.n, mi * R,
-                       wk.nrm);
+    const unsigned nb = red_blocks(md.hp.n);
+    hipLaunchKernelGGL(k_norm2_part, dim3(nb, R), dim3(kRed), 0, c.s, wk.w, ld, md.offset,
+                       md.offset + md.hp.n, mi * R, wk.npart);
+    LAUNCHCHECK();
+    hipLaunchKernelGGL(k_normalize_next, dim3(nblk(md.hp.n, 256), R), dim3(256), 0, c.s, wk.w,
+                       wk.V + (j + 1) * vstride, wk.z, c.dinv, ld, md.offset, md.offset + md.hp.n,
+                       mi * R, wk.npart, (int)nb, wk.nrm);
     LAUNCHCHECK();
     ++mi;
   }
