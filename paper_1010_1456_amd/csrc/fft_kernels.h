@@ -138,18 +138,22 @@ __global__ void __launch_bounds__((threads_contig<T, PC>()))
     constexpr bool first = (s == 0), last = (s == PC::ns - 1);
     const int b = threadIdx.x / nb, beta = threadIdx.x - b * nb;
     const bool active = (b < B) && (line0 + b < lines);
-    const V *gin = in + contig_base(imap, line0 + b);
-    V *gout = out + contig_base(omap, line0 + b);
+    // threads past the last line address the last line (the line selection
+    // and range tables are read for every thread; nothing is loaded or
+    // stored for them)
+    const int64_t Lc = active ? line0 + b : lines - 1;
+    const V *gin = in + contig_base(imap, Lc);
+    V *gout = out + contig_base(omap, Lc);
     V *ll = lds + b * LS;
     (void)tw;
     int in_lo = 0, in_hi = n_in, out_lo = 0, out_hi = n_out;
     if (first && imap.range) {
-      const int64_t r = (line0 + b) % imap.nsel;
+      const int64_t r = sel_index(imap, Lc);
       in_lo = imap.range[2 * r];
       in_hi = min(n_in, imap.range[2 * r + 1]);
     }
     if (last && omap.range) {
-      const int64_t r = (line0 + b) % omap.nsel;
+      const int64_t r = sel_index(omap, Lc);
       out_lo = omap.range[2 * r];
       out_hi = min(n_out, omap.range[2 * r + 1]);
     }

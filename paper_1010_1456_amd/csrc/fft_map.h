@@ -75,8 +75,20 @@ struct ContigMap {
   // range[2 s] <= i < range[2 s + 1] only (the others read as zero on input,
   // are not stored on output)
   const int32_t *range = nullptr;
+  // fin > 0: fields innermost in the pass numbering, L = l fin + f (the
+  // fields of one line are consecutive pass lines): line l (through sel if
+  // given, sel index l) of field f starts at f fs + l ls; per is unused
+  int64_t fin = 0;
 };
+// index into sel / range of pass line L
+__host__ __device__ inline int64_t sel_index(const ContigMap &m, int64_t L) {
+  return m.fin ? L / m.fin : L % m.nsel;
+}
 __host__ __device__ inline int64_t contig_base(const ContigMap &m, int64_t L) {
+  if (m.fin) {
+    const int64_t f = L % m.fin, l = L / m.fin;
+    return f * m.fs + (m.sel ? (int64_t)m.sel[l] : l) * m.ls;
+  }
   if (m.sel) {
     const int64_t f = L / m.nsel;
     L = f * m.sper + m.sel[L - f * m.nsel];
@@ -90,6 +102,19 @@ inline ContigMap contig_map(int64_t ls) { return ContigMap{0, 0, ls, 1}; }
 // per lines of each of the fields fs apart, lines ls apart, elements es apart
 inline ContigMap contig_map(int64_t per, int64_t fs, int64_t ls, int64_t es) {
   return ContigMap{per, fs, ls, es};
+}
+// fields innermost: line l of field f at f fs + l ls (pass line l fin + f),
+// elements es apart, optionally over the selected lines sel[0 .. nsel) and
+// their element ranges
+inline ContigMap fields_inner(int64_t fin, int64_t fs, int64_t ls, int64_t es,
+                              const int32_t *sel = nullptr, int64_t nsel = 0,
+                              const int32_t *range = nullptr) {
+  ContigMap m{0, fs, ls, es};
+  m.fin = fin;
+  m.sel = sel;
+  m.nsel = nsel;
+  m.range = range;
+  return m;
 }
 // the same map over the selected lines sel[0 .. nsel) of each field of sper lines
 inline ContigMap select_lines(ContigMap m, const int32_t *sel, int64_t nsel, int64_t sper,

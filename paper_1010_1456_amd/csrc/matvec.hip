@@ -162,7 +162,7 @@ constexpr int kNearUnroll = 4;
 // eta_h = (1 - alpha) eta; the curl weights W test the vector potential's curl.
 template <typename T, typename TX, typename TY, int RB, bool CF>
 __global__ void __launch_bounds__(256)
-    k_interp_near(const cx<T> *__restrict__ phi, int64_t V0, int nrhs, const T *__restrict__ lam,
+    k_interp_near(const cx<T> *__restrict__ phi, int64_t nf, int nrhs, const T *__restrict__ lam,
                   const T *__restrict__ curl, const int32_t *__restrict__ anchor_lin,
                   const int32_t *__restrict__ soff, int K, const int32_t *__restrict__ rowptr,
                   const int32_t *__restrict__ cols, const cx<T> *__restrict__ nearv,
@@ -191,8 +191,8 @@ __global__ void __launch_bounds__(256)
     }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
-      const V *ph = phi + (int64_t)((r0 + rb) * 4) * V0 + o;
-      const V p0 = ph[0], p1 = ph[V0], p2 = ph[2 * V0], p3 = ph[3 * V0];
+      const V *ph = phi + o * nf + (r0 + rb) * 4;  // fields interleaved per node
+      const V p0 = ph[0], p1 = ph[1], p2 = ph[2], p3 = ph[3];
       far[rb].x += l0 * p0.x + l1 * p1.x + l2 * p2.x - inv_k2 * l3 * p3.x;
       far[rb].y += l0 * p0.y + l1 * p1.y + l2 * p2.y - inv_k2 * l3 * p3.y;
       if (CF) {
@@ -427,8 +427,9 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
                  tw_of<T>(md, 0), 0, V2, s);
     mark(4);
     if (stop <= 4) return;
-    fft_pass_contig(g2, g0, md.plan[1], Py, Ny, F * Nx, fftk::contig_map(Py), fftk::contig_map(Ny),
-                    true, tw_of<T>(md, 1), s);
+    // into the field-interleaved plane [Nx][Ny][F] the interpolation reads
+    fft_pass_contig(g2, g0, md.plan[1], Py, Ny, F * Nx, fftk::fields_inner(F, (int64_t)Nx * Py, Py, 1),
+                    fftk::fields_inner(F, 1, (int64_t)Ny * F, F), true, tw_of<T>(md, 1), s);
     mark(5);
     mark(6);
     return;
@@ -472,10 +473,11 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
       fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * A1, fftk::contig_map(A1, V1, 1, A1),
                       fftk::contig_map(Nz), true, tw_of<T>(md, 2), s);
     } else {  // the lines the interpolation reads
+      // into the field-interleaved grid [Nx][Ny][Nz][F]
       const int64_t nl = md.n_occ_lines;
       fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * nl,
-                      fftk::select_lines(fftk::contig_map(A1, V1, 1, A1), md.occ_lines, nl, A1),
-                      fftk::select_lines(fftk::contig_map(Nz), md.occ_lines, nl, A1), true,
+                      fftk::fields_inner(F, V1, 1, A1, md.occ_lines, nl),
+                      fftk::fields_inner(F, 1, (int64_t)Nz * F, F, md.occ_lines, nl), true,
                       tw_of<T>(md, 2), s);
     }
     mark(6);
@@ -542,10 +544,12 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * Nx * Ny, fftk::contig_map(Pzs),
                     fftk::contig_map(Nz), true, tw_of<T>(md, 2), s);
   } else {  // the lines the interpolation reads
-    const int64_t nl = md.n_occ_lines, A1 = (int64_t)Nx * Ny;
+    // into the field-interleaved grid [Nx][Ny][Nz][F]: the four fields of a
+    // right-hand side at a stencil node are one 32-byte (c64) read
+    const int64_t nl = md.n_occ_lines;
     fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * nl,
-                    fftk::select_lines(fftk::contig_map(Pzs), md.occ_lines, nl, A1),
-                    fftk::select_lines(fftk::contig_map(Nz), md.occ_lines, nl, A1, md.occ_zrange),
+                    fftk::fields_inner(F, V1, Pzs, 1, md.occ_lines, nl),
+                    fftk::fields_inner(F, 1, (int64_t)Nz * F, F, md.occ_lines, nl, md.occ_zrange),
                     true, tw_of<T>(md, 2), s);
   }
   mark(6);
@@ -559,8 +563,7 @@ void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, 
   far_stages<T, TX>(pl, md, nrhs, x, ldx, 6, s, ev);
   const cx<T> *phi = (const cx<T> *)pl->work[prec][0];
   const bool plane = md.planar_z >= 0;  // fields on the scatterer's grid plane only
-  const int64_t V0 = plane ? (int64_t)h.grid[0] * h.grid[1]
-                           : (int64_t)h.grid[0] * h.grid[1] * h.grid[2];
+  const int64_t nf = 4 * (int64_t)nrhs;  // fields per node of the interleaved grid
   const int rows_per_block = 8;
   const int64_t blocks = (h.n + rows_per_block - 1) / rows_per_block;
   // right-hand sides per grid row: 4 or 2 when they divide nrhs
@@ -569,7 +572,7 @@ void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, 
   if (cf && (plane || !curl_of<T>(md))) throw Error(AIM_ERR_STATE, "combined field without curl weights");
   auto launch = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks, nrhs / rb), dim3(32 * rows_per_block), 0, s,
-                       phi, V0, nrhs, plane ? plane_lam_of<T>(md) : lam_of<T>(md),
+                       phi, nf, nrhs, plane ? plane_lam_of<T>(md) : lam_of<T>(md),
                        cf ? curl_of<T>(md) : nullptr, plane ? md.plane_anchor : md.anchor_lin,
                        plane ? md.plane_soff : md.stencil_off, plane ? md.plane_K : h.K,
                        md.rowptr, md.cols, near_of<T>(md), x, ldx, y, ldy, h.n,
