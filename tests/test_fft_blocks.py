@@ -48,3 +48,21 @@ def test_every_radix_and_direction(lines):
         ref = np.fft.ifft(x) * R if inv else np.fft.fft(x)
         g = np.array([got[k] for k in range(R)])
         assert np.abs(g - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()), (R, inv, uz)
+
+
+def test_line_maps_stay_in_bounds():
+    """Line selection with fields innermost or field-major, as the z passes
+    use them: every pass line, and the clamped line of threads past the last
+    one, reads an in-bounds selection entry and addresses an in-bounds line
+    (a tail thread once read past the selection table)."""
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "fft_map_check")
+        subprocess.run([_hipcc(), "-O1", "-std=c++17", "-x", "hip", "--offload-arch=gfx950",
+                        "-I", CSRC, os.path.join(HERE, "fft_map_check.cpp"), "-o", exe],
+                       check=True, capture_output=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    rows = [ln.split() for ln in out.splitlines()]
+    assert len(rows) == 9
+    for name, max_sel, nsel, max_first, max_last, limit in rows:
+        assert int(max_sel) == int(nsel) - 1, name
+        assert 0 <= int(max_first) and int(max_last) < int(limit), name
