@@ -512,6 +512,7 @@ def main(argv=None):
             "systems_per_product": info["nmesh"] * R,
             "precision": "c64 grid/stencil/near arithmetic on c128 vectors (mixed path)",
             "fused_projection": info["fused_projection"][0][1],
+            "gather_nodes_per_wave": info["gather_npw"][0][1],
         },
         "roofline": {
             "bound": "hbm",

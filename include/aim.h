@@ -183,6 +183,8 @@ typedef struct {
                                            interpolation reads; plane nodes for planar_z >= 0) */
   int64_t occ_lines[AIM_MAX_MESH];      /* z lines (x, y) holding such a node (the only lines
                                            the z passes transform) */
+  int32_t gather_npw[AIM_MAX_MESH][2];  /* [mesh][0 FP64, 1 mixed]: occupied nodes per wave of
+                                           the projection gather (chosen by timing at set-up) */
 } aim_info;
 
 /* GMRES options. restart m (<= 200), relative-residual tolerance on

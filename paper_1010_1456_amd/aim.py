@@ -87,7 +87,8 @@ class AimInfo(ctypes.Structure):
                 ("bytes_fp64", c_double * M), ("bytes_mixed", c_double * M),
                 ("fused_projection", (c_int32 * 2) * M), ("planar_z", c_int32 * M),
                 ("device_bytes", c_double), ("setup_ms", (c_double * AIM_NSETUP) * M),
-                ("cfie_alpha", c_double * M), ("occ_nodes", c_int64 * M), ("occ_lines", c_int64 * M)]
+                ("cfie_alpha", c_double * M), ("occ_nodes", c_int64 * M), ("occ_lines", c_int64 * M),
+                ("gather_npw", (c_int32 * 2) * M)]
 
 
 class AimSolveOpts(ctypes.Structure):
@@ -291,7 +292,8 @@ class Plan:
             setup_ms=[dict(zip(SETUP_PHASES, inf.setup_ms[i])) for i in range(nm)],
             cfie_alpha=[None if inf.cfie_alpha[i] < 0 else inf.cfie_alpha[i] for i in range(nm)],
             occ_nodes=[inf.occ_nodes[i] for i in range(nm)],
-            occ_lines=[inf.occ_lines[i] for i in range(nm)])
+            occ_lines=[inf.occ_lines[i] for i in range(nm)],
+            gather_npw=[tuple(inf.gather_npw[i]) for i in range(nm)])
 
     def _stream(self, stream):
         s = stream if stream is not None else self._torch.cuda.current_stream()

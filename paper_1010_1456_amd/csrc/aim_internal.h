@@ -173,7 +173,9 @@ struct MeshDev {
   int32_t *plane_anchor = nullptr;    // n
   int32_t *plane_soff = nullptr;      // (M+1)^2
   int plane_K = 0;                    // (M+1)^2
-  int plane_npw = 16;                 // plane nodes per wave of the gather
+  // occupied nodes per wave of the projection gather, per precision [FP64,
+  // FP32]: chosen by timing at set-up among 8, 16, 32
+  int gather_npw[2] = {16, 16};
   double setup_ms[AIM_NSETUP] = {0, 0, 0, 0, 0};  // wall time per set-up phase
   // combined field only: curl weights W[n][e][u] = int (t_n x grad l_u)_e,
   // t_n = f_n x n (the MFIE part is interpolated from the vector potential's

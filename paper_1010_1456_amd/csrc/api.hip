@@ -233,6 +233,8 @@ aim_status aim_plan_info(const aim_plan *plan, aim_info *out) {
     out->cfie_alpha[i] = md.hp.cfie ? md.hp.alpha : -1.0;
     out->occ_nodes[i] = md.planar_z >= 0 ? md.n_plane_occ : md.n_occ;
     out->occ_lines[i] = md.n_occ_lines;
+    out->gather_npw[i][0] = md.gather_npw[0];
+    out->gather_npw[i][1] = md.gather_npw[1];
     for (int j = 0; j < AIM_NSETUP; ++j) out->setup_ms[i][j] = md.setup_ms[j];
   }
   out->device_bytes = plan->device_bytes;

@@ -32,7 +32,9 @@ constexpr int anterp_epl() {
   return 2;
 }
 // occupied nodes per wave of the 3-D projection
-constexpr int kGatherNpw = 16;  // (measured on the sphere: 64 0.079 ms, 32 0.067, 16 0.058, 8 0.056 c64 but slower c128)
+// occupied nodes per wave of the gather: candidates timed at set-up (on the
+// sphere: 64 0.079 ms, 32 0.067, 16 0.058, 8 0.056 for c64; 16 best for c128)
+constexpr int kGatherNpwCand[3] = {8, 16, 32};
 // With occ (the occupied nodes, increasing) the wave walks npw consecutive
 // occupied nodes instead: node_ptr is then their compacted entry ranges, V0
 // their count, and node i is written at grid index occ[i] of fields of Vg
@@ -399,6 +401,7 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
   const int64_t F = 4 * (int64_t)nrhs;
   const int64_t V0 = (int64_t)Nx * Ny * Nz;
   const int blk = kGridBlock<T>;
+  const int npw = md.gather_npw[prec];
   if (md.planar_z >= 0 && !full3d) {
     // every source on the plane z = planar_z, and only that plane weighted by
     // the interpolation: the plane alone, g0 = [F][Nx][Ny], 2-D propagation
@@ -411,9 +414,9 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     const int64_t no = md.n_plane_occ;
     if (no > 0) {
       hipLaunchKernelGGL((k_anterp_gather<T, TX>),
-                         dim3((unsigned)((no + 4 * md.plane_npw - 1) / (4 * md.plane_npw)), nrhs),
+                         dim3((unsigned)((no + 4 * npw - 1) / (4 * npw)), nrhs),
                          dim3(256), 0, s, x, ldx, nrhs, md.plane_occ_ptr, md.plane_occ,
-                         md.ent_col, lamT_of<T>(md), gs, no, A1, md.plane_npw);
+                         md.ent_col, lamT_of<T>(md), gs, no, A1, npw);
       LAUNCHCHECK();
     }
     mark(1);
@@ -446,9 +449,9 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     mark(0);
     if (md.n_occ > 0) {
       hipLaunchKernelGGL((k_anterp_gather<T, TX>),
-                         dim3((unsigned)((md.n_occ + 4 * kGatherNpw - 1) / (4 * kGatherNpw)), nrhs),
+                         dim3((unsigned)((md.n_occ + 4 * npw - 1) / (4 * npw)), nrhs),
                          dim3(256), 0, s, x, ldx, nrhs, md.occ_ptr, md.occ, md.ent_col,
-                         lamT_of<T>(md), gs, md.n_occ, V0, kGatherNpw);
+                         lamT_of<T>(md), gs, md.n_occ, V0, npw);
       LAUNCHCHECK();
     }
     mark(1);
@@ -504,9 +507,9 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     cx<T> *gs = src_buffer<T>(pl, md, sizeof(cx<T>) * F * V0, s);
     if (md.n_occ > 0) {
       hipLaunchKernelGGL((k_anterp_gather<T, TX>),
-                         dim3((unsigned)((md.n_occ + 4 * kGatherNpw - 1) / (4 * kGatherNpw)), nrhs),
+                         dim3((unsigned)((md.n_occ + 4 * npw - 1) / (4 * npw)), nrhs),
                          dim3(256), 0, s, x, ldx, nrhs, md.occ_ptr, md.occ, md.ent_col,
-                         lamT_of<T>(md), gs, md.n_occ, V0, kGatherNpw);
+                         lamT_of<T>(md), gs, md.n_occ, V0, npw);
       LAUNCHCHECK();
     }
     mark(1);
@@ -644,6 +647,35 @@ void autotune_mesh(Plan *pl, MeshDev &md, hipStream_t s) {
   try {
     x = dev_alloc(pl, sizeof(double2) * n);
     HIPCHECK(hipMemsetAsync(x, 0, sizeof(double2) * n, s));
+    auto time_stages = [&](int prec, int stop) {
+      for (int rep = 0; rep < 4; ++rep) {  // first repetition is a warm-up
+        if (rep == 1) HIPCHECK(hipEventRecord(e0, s));
+        if (prec == 0)
+          far_stages<double, double>(pl, md, 1, (const double2 *)x, n, stop, s);
+        else
+          far_stages<float, double>(pl, md, 1, (const double2 *)x, n, stop, s);
+      }
+      HIPCHECK(hipEventRecord(e1, s));
+      HIPCHECK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+      return ms;
+    };
+    // projection gather: occupied nodes per wave
+    for (int prec = 0; prec < 2; ++prec) {
+      if (prec == 1 && !pl->mixed) break;
+      float best = 0;
+      int choice = kGatherNpwCand[1];
+      for (int c = 0; c < 3; ++c) {
+        md.gather_npw[prec] = kGatherNpwCand[c];
+        const float ms = time_stages(prec, 1);
+        if (c == 0 || ms < best) {
+          best = ms;
+          choice = kGatherNpwCand[c];
+        }
+      }
+      md.gather_npw[prec] = choice;
+    }
     for (int prec = 0; prec < 2; ++prec) {
       if (prec == 1 && !pl->mixed) break;
       const bool thin = prec == 0 ? thin_layout<double>(md.hp.pad[2]) : thin_layout<float>(md.hp.pad[2]);
@@ -655,17 +687,7 @@ void autotune_mesh(Plan *pl, MeshDev &md, hipStream_t s) {
       int choice = 0;
       for (int v = 0; v < 2; ++v) {
         md.fuse_proj[prec] = v;
-        for (int rep = 0; rep < 4; ++rep) {  // first repetition is a warm-up
-          if (rep == 1) HIPCHECK(hipEventRecord(e0, s));
-          if (prec == 0)
-            far_stages<double, double>(pl, md, 1, (const double2 *)x, n, 2, s);
-          else
-            far_stages<float, double>(pl, md, 1, (const double2 *)x, n, 2, s);
-        }
-        HIPCHECK(hipEventRecord(e1, s));
-        HIPCHECK(hipEventSynchronize(e1));
-        float ms = 0;
-        HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+        const float ms = time_stages(prec, 2);
         if (v == 0 || ms < best) {
           best = ms;
           choice = v;
