@@ -571,7 +571,9 @@ void run_segment_graph(Plan *pl, SolverState &st, Ctx &c, aim_precision prec, in
 }
 
 // Solve A d = rhs (d starts at 0) for every system to a relative residual
-// tol_s (estimated by the Arnoldi recurrence), restarted every m steps. The
+// tol_s (estimated by the Arnoldi recurrence), restarted every m steps; a
+// low-precision run also stops a system whose true residual has reached the
+// operator's rounding floor (see the restart check). The
 // Arnoldi step, the rotations and the residual estimate stay on the device;
 // the host reads the active flags every kCheckEvery iterations. Returns the
 // iterations used (lock-step count); `its` per system, `nprod` products.
@@ -588,9 +590,9 @@ int gmres_run(Ctx &c, SolverState &st, aim_precision prec, bool graphs, const do
   for (int s = 0; s < S; ++s)
     if (rhs_norm2[s] == 0.0) done[s] = 1;
   int total = 0;
-  std::vector<double> r2;
+  std::vector<double> r2, prev(S, 0.0);
   bool first_cycle = true;
-  std::vector<int> act(S), itd(S);
+  std::vector<int> act(S), itd(S), jendh(S, m);
   HIPCHECK(hipMemcpyAsync(wk.dev.its, its.data(), sizeof(int) * S, hipMemcpyHostToDevice, c.s));
   while (true) {
     // residual of the current iterate: r = rhs - A d (rhs itself on the first cycle)
@@ -602,11 +604,19 @@ int gmres_run(Ctx &c, SolverState &st, aim_precision prec, bool graphs, const do
       hipLaunchKernelGGL(k_residual, dim3(nblk(cnt, 256)), dim3(256), 0, c.s, rhs, wk.w, cnt);
       LAUNCHCHECK();
     }
+    const bool restarted = !first_cycle;
     first_cycle = false;
     norms(c, wk.w, wk.npart, wk.nrm, r2);
     bool all = true;
     for (int s = 0; s < S; ++s) {
       if (!done[s] && r2[s] <= tol_s[s] * tol_s[s] * rhs_norm2[s]) done[s] = 1;
+      // Low-precision operator at its rounding floor: the last cycle's
+      // estimate met the tolerance before the restart length, yet the true
+      // residual of this operator did not even halve. Further cycles only
+      // chase rounding noise; the FP64 refinement around this run continues.
+      if (!done[s] && restarted && prec != AIM_FP64 && jendh[s] < m && r2[s] > 0.25 * prev[s])
+        done[s] = 1;
+      prev[s] = r2[s];
       all &= (bool)done[s];
     }
     if (all || total >= max_iter) break;
@@ -667,6 +677,7 @@ int gmres_run(Ctx &c, SolverState &st, aim_precision prec, bool graphs, const do
         ++mi;
       }
     }
+    HIPCHECK(hipMemcpyAsync(jendh.data(), wk.dev.jend, sizeof(int) * S, hipMemcpyDeviceToHost, c.s));
     HIPCHECK(hipStreamSynchronize(c.s));
   }
   HIPCHECK(hipMemcpyAsync(itd.data(), wk.dev.its, sizeof(int) * S, hipMemcpyDeviceToHost, c.s));
