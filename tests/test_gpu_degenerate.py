@@ -128,3 +128,62 @@ def test_solve_is_b_over_z00(prec):
         assert abs(x[i, 0] - xo[0]) <= (1e-10 if prec == "fp64" else 1e-5) * abs(xo[0])
         so = off.sigma_tt(s.rwg, s.k, xo, th, ph)
         assert np.abs(sig[i] - so).max() <= (1e-9 if prec == "fp64" else 3e-5) * np.abs(so).max()
+
+
+# Scatterers a few tenths of a wavelength across: every grid dimension pads
+# to at most 8, so every FFT pass (z, y and the x pass with the spectrum) runs
+# its one-stage kernels, odd (5) and even (8, half-pruned) lengths; every
+# basis pair is near, so the product is Z^MOM x to rounding.
+def _square_03():
+    return VERTS, TRIS, 0.3e9
+
+
+def _sphere(radius, nf):
+    def make():
+        from workloads import sphere_mesh
+
+        m = sphere_mesh(radius, 0.3e9, nf=nf)
+        return m.verts, m.tris, m.freq_hz
+
+    return make
+
+
+SMALL = {"square_5": (_square_03, (5, 5, 5)), "sphere_n30_5": (_sphere(0.1, 1), (5, 5, 5)),
+         "sphere_n120_8": (_sphere(0.15, 2), (8, 8, 8))}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_single_stage_ffts(name):
+    from paper_1010_1456_amd import aim as A
+
+    make, pad = SMALL[name]
+    verts, tris, freq = make()
+    k = wavenumber(freq)
+    lam = wavelength(freq)
+    rwg = build_rwg(verts, tris)
+    op = oaim.build_operator(rwg, k, 0.1 * lam, 2, 0.3 * lam)
+    _log(f"[small {name}] GPU set-up N={rwg.n}")
+    plan = A.Plan([(verts, tris, freq)])
+    assert tuple(plan.info()["pad"][0]) == pad
+    Z = omom.dense_z(rwg, k)
+    x = np.random.default_rng(11).normal(size=(2, rwg.n)) * (1 + 0.5j)
+    x += 1j * np.random.default_rng(12).normal(size=(2, rwg.n))
+    xd = torch.from_numpy(x).cuda()
+    y64 = plan.matvec(xd, A.AIM_FP64).cpu().numpy()
+    y32 = plan.matvec(xd, A.AIM_MIXED_IO64).cpu().numpy()
+    for r in range(2):
+        ref = oaim.matvec_fft(op, x[r])
+        assert np.linalg.norm(ref - Z @ x[r]) <= 1e-10 * np.linalg.norm(ref)  # all pairs near
+        assert np.linalg.norm(y64[r] - ref) <= 1e-10 * np.linalg.norm(ref), r
+        assert np.linalg.norm(y32[r] - ref) <= 2e-5 * np.linalg.norm(ref), r
+    # the solve against a dense LU solve of the same system
+    wave = (0.3, 0.2, 0)
+    b = oexc.planewave_rhs(rwg, k, *wave)
+    xo = np.linalg.solve(Z, b)
+    for P, tol in ((A.AIM_FP64, 1e-9), (A.AIM_MIXED, 1e-7)):
+        xs, st = plan.solve([wave], P, tol=tol)
+        xs = xs.cpu().numpy()[0]
+        assert st[0]["converged"], P
+        # relative error <= cond(Z) * residual; cond is modest for these meshes
+        assert np.linalg.norm(xs - xo) <= 1e3 * tol * np.linalg.norm(xo), P
+    plan.close()
