@@ -167,3 +167,20 @@ def test_cfie_needs_a_closed_outward_mesh():
             lib_aim.host_plan(verts, tris, m.freq_hz, cfie_alpha=alpha)
         assert e.value.status == status
         lib_aim.host_plan(verts, tris, m.freq_hz)
+
+
+def test_grid_size_limits():
+    """Two triangles spanning 170 lambda need a 1703-node grid, whose padded
+    length 3456 is the largest compiled FFT; 180 lambda needs more and is
+    refused with AIM_ERR_ARG before anything is allocated."""
+    tris = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)
+
+    def square(side):
+        return np.array([[0, 0, 0], [side, 0, 0], [side, side, 0], [0, side, 0]], dtype=float)
+
+    hp = lib_aim.host_plan(square(170.0), tris, 0.3e9)
+    assert list(hp["grid"]) == [1703, 1703, 3] and list(hp["pad"]) == [3456, 3456, 5]
+    with pytest.raises(lib_aim.AimError) as e:
+        lib_aim.host_plan(square(180.0), tris, 0.3e9)
+    assert e.value.status == lib_aim.AIM_ERR_ARG
+    assert "largest supported FFT length" in str(e.value)
