@@ -264,7 +264,9 @@ aim_status aim_matvec_timed(aim_plan *plan, aim_precision prec, int32_t nrhs, co
  * (waves: host, nrhs_per_mesh entries, the same set for every mesh) with
  * restarted GMRES, right Jacobi preconditioning D = diag(Z^MOM), FP64
  * (classical Gram-Schmidt, twice) Arnoldi and, for AIM_MIXED, an FP64 outer
- * refinement loop r = b - A64 x around inner solves with the c64 operator.
+ * refinement loop r = b - A64 x around inner solves with the c64 operator
+ * (at most 20 refinement steps; an inner solve ends at its target or where
+ * the c64 operator's rounding stops its true residual from falling).
  * x_io: device c128 [n_total][nrhs_per_mesh]. stats: host
  * [nrhs_per_mesh] (per wave, worst over meshes) or NULL. Synchronises.
  * Returns AIM_ERR_NOCONV if some right-hand side missed tol (x_io then holds
