@@ -189,3 +189,112 @@ def test_dense_mom_sphere_against_mie():
     delta = np.linalg.norm(Z - Z.T) / np.linalg.norm(Z)
     lhs, rhs = V @ Ib, Vb @ I
     assert abs(lhs - rhs) <= 10 * delta * abs(lhs) + 1e-12
+
+
+def _pair_classes(rwg):
+    """Per basis pair: 2 = identical or sharing a triangle edge (a common
+    triangle or a common edge between their triangles), 1 = only a vertex in
+    common, 0 = no common vertex."""
+    tri_v = [set(rwg.tris[rwg.tplus[n]]) | set(rwg.tris[rwg.tminus[n]]) for n in range(rwg.n)]
+    tri_sets = [[set(rwg.tris[rwg.tplus[n]]), set(rwg.tris[rwg.tminus[n]])] for n in range(rwg.n)]
+    cls = np.zeros((rwg.n, rwg.n), dtype=np.int8)
+    for a in range(rwg.n):
+        for b in range(rwg.n):
+            if not (tri_v[a] & tri_v[b]):
+                continue
+            shared = max(len(s & t) for s in tri_sets[a] for t in tri_sets[b])
+            cls[a, b] = 2 if shared >= 2 else 1
+    return cls
+
+
+def test_z_entries_equal_dense_matrix():
+    """oracle.mom.z_entries (the near-zone reference of the full-size parity
+    tests) equals the dense EFIE matrix entry by entry, on self, edge-touching,
+    vertex-touching and separated pairs of a 0.4-lambda sphere."""
+    m = sphere_mesh(0.4, F, nf=3, jitter_seed=11)
+    rwg = build_rwg(m.verts, m.tris)
+    Z = mom.dense_z(rwg, K)
+    cls = _pair_classes(rwg)
+    rng = np.random.default_rng(5)
+    rows, cols = [], []
+    diag = rng.choice(rwg.n, 30, replace=False)
+    rows += list(diag)
+    cols += list(diag)
+    for c in (2, 1, 0):
+        a, b = np.nonzero(cls == c)
+        off = a != b
+        a, b = a[off], b[off]
+        pick = rng.choice(a.size, 70, replace=False)
+        rows += list(a[pick])
+        cols += list(b[pick])
+    rows, cols = np.array(rows), np.array(cols)
+    assert rows.size >= 200
+    z = mom.z_entries(rwg, K, rows, cols)
+    ref = Z[rows, cols]
+    np.testing.assert_allclose(z, ref, rtol=1e-14, atol=1e-14 * np.abs(Z).max())
+
+
+def _rhat(theta, phi):
+    return np.array([math.sin(theta) * math.cos(phi), math.sin(theta) * math.sin(phi),
+                     math.cos(theta)])
+
+
+def _pol_vector(theta, phi, pol):
+    """theta_hat = d r_hat / d theta, phi_hat = (d r_hat / d phi) / sin(theta),
+    by central differences of r_hat (independent of the excitation code)."""
+    e = 1e-6
+    if pol == 0:
+        v = (_rhat(theta + e, phi) - _rhat(theta - e, phi)) / (2 * e)
+    else:
+        v = (_rhat(theta, phi + e) - _rhat(theta, phi - e)) / (2 * e * math.sin(theta))
+    return v
+
+
+OBLIQUE_WAVES = [(0.4, 0.3, 0), (0.4, 0.3, 1), (1.1, 2.2, 0), (1.1, 2.2, 1), (2.3, -0.7, 0),
+                 (2.3, -0.7, 1), (2.9, 4.0, 0), (2.9, 4.0, 1)]
+
+
+def _rhs_reciprocity_errors(rwg):
+    """max over waves of max_m |V_m - p_hat . N_m(r_hat)| / max |V|, with N_m
+    the radiation vector of the unit current on basis m: a plane wave arriving
+    from r_hat has phase exp(-j k k_hat . r) = exp(+j k r_hat . r), the
+    radiation vector's kernel, so V_m = p_hat . N_m(r_hat)."""
+    errs = []
+    for th, ph, pol in OBLIQUE_WAVES:
+        V = excitation.planewave_rhs(rwg, K, th, ph, pol)
+        p = _pol_vector(th, ph, pol)
+        ref = np.empty(rwg.n, dtype=np.complex128)
+        for n in range(rwg.n):
+            e = np.zeros(rwg.n, dtype=np.complex128)
+            e[n] = 1.0
+            Nv = farfield.radiation_vector(rwg, K, e, np.array([th]), np.array([ph]))[0, 0]
+            ref[n] = p @ Nv
+        errs.append(np.abs(V - ref).max() / np.abs(ref).max())
+    return max(errs)
+
+
+@pytest.mark.parametrize("kind", ["sphere", "plate"])
+def test_oblique_incidence_rhs_is_radiation_vector(kind):
+    """Oblique plane-wave right-hand sides, both polarisations, every basis:
+    V_m = p_hat(theta_i, phi_i) . N_m(r_hat(theta_i, phi_i)) (the radiation
+    vector is pinned against the direct field above)."""
+    m = (sphere_mesh(0.4, F, nf=3, jitter_seed=12) if kind == "sphere"
+         else plate_mesh(1.0, F, squares_per_lambda=5, jitter_seed=13))
+    rwg = build_rwg(m.verts, m.tris)
+    assert _rhs_reciprocity_errors(rwg) < 1e-9
+
+
+@pytest.mark.parametrize("plant", ["theta_hat", "k_hat"])
+def test_oblique_rhs_check_catches_planted_errors(monkeypatch, plant):
+    """A sign flip planted in the oracle's unit vectors (theta_hat, or the
+    propagation direction k_hat = -r_hat) makes the identity above fail."""
+    m = sphere_mesh(0.4, F, nf=2, jitter_seed=12)
+    rwg = build_rwg(m.verts, m.tris)
+    orig = excitation.unit_vectors
+
+    def planted(theta, phi):
+        r, t, p = orig(theta, phi)
+        return (r, -t, p) if plant == "theta_hat" else (-r, t, p)
+
+    monkeypatch.setattr(excitation, "unit_vectors", planted)
+    assert _rhs_reciprocity_errors(rwg) > 0.1
