@@ -187,6 +187,10 @@ struct MeshDev {
   // projection writes the occupied nodes only (the same nodes every product)
   void *src[2] = {nullptr, nullptr};
   size_t src_bytes[2] = {0, 0};
+  // field layout the source grid was last written in (0 none, 1 the 3-D grid
+  // [4 nrhs][V0], 2 the plane [4 nrhs][Nx Ny]): the zero nodes of one layout
+  // are not those of the other, so a change of layout clears the buffer
+  int src_layout[2] = {0, 0};
   // forward z transforms of those grids per precision [4 nrhs][Nx Ny][Pzs]
   // (kz-blocked grids only): zero once, after which the forward z pass
   // writes the occupied z lines only
@@ -261,13 +265,31 @@ AIM_DECLARE_ANTERP(double2, float, float2)
 AIM_DECLARE_ANTERP(double2, double, double2)
 #undef AIM_DECLARE_ANTERP
 
+// Where the product left the grid after one of its stages (inspection):
+// element (f, a, z) of the plain [F][A][Z] view is p[f fs + a as + z zs]
+// (kind 1), or the kz-blocked grid [F][Z/blk][Nx][Py][blk] with fstride
+// between fields and A = Nx Py (kind 2); kind 0: no such stage.
+struct StageView {
+  const void *p = nullptr;
+  int kind = 0;
+  int64_t F = 0, A = 0, Z = 0, fs = 0, as = 0, zs = 0;
+  int Nx = 0, Py = 0, blk = 0;
+  int64_t fstride = 0;
+};
+
 // matvec (matvec.hip)
 // `ev` (optional) receives an event record before the first kernel and after
 // each stage: ev[0] .. ev[AIM_NSTAGE]. `full3d` (inspection): the 3-D passes
-// also for a scatterer in one grid plane.
+// also for a scatterer in one grid plane. `views` (optional, AIM_NSTAGE
+// entries, index = stage): where the product's own passes left each stage's
+// output.
 template <typename T, typename TX>
 void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, int stop_stage,
-                hipStream_t s, hipEvent_t *ev = nullptr, bool full3d = false);
+                hipStream_t s, hipEvent_t *ev = nullptr, bool full3d = false,
+                StageView *views = nullptr);
+// copies a stage's output as recorded in `v` to out in the plain [F][A][Z] layout
+template <typename T>
+void copy_stage_view(const StageView &v, void *out, hipStream_t s);
 template <typename T, typename TX, typename TY>
 void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, cx<TY> *y,
                  int64_t ldy, hipStream_t s, hipEvent_t *ev = nullptr);

@@ -354,10 +354,23 @@ static cx<T> *zeroed_buffer(Plan *pl, void *(&buf)[2], size_t (&have)[2], size_t
   }
   return (cx<T> *)buf[prec];
 }
-// the mesh's projected source grid, zero where no projection entry lands
+// the mesh's projected source grid in `layout` (1: 3-D grid [F][V0], 2: the
+// scatterer's plane [F][Nx Ny]), zero where no projection entry lands. The
+// projection writes the occupied nodes only, so a buffer last written in the
+// other layout (the full 3-D inspection of a planar scatterer, or the plane
+// after it) is cleared first.
 template <typename T>
-static cx<T> *src_buffer(Plan *pl, MeshDev &md, size_t bytes, hipStream_t s) {
-  return zeroed_buffer<T>(pl, md.src, md.src_bytes, bytes, s);
+static cx<T> *src_buffer(Plan *pl, MeshDev &md, size_t bytes, int layout, hipStream_t s) {
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  const size_t had = md.src_bytes[prec];
+  cx<T> *p = zeroed_buffer<T>(pl, md.src, md.src_bytes, bytes, s);
+  if (md.src_bytes[prec] == had && md.src_layout[prec] != layout) {  // not just zeroed
+    const int64_t n = (int64_t)(had / sizeof(cx<T>));
+    hipLaunchKernelGGL((k_zero<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    LAUNCHCHECK();
+  }
+  md.src_layout[prec] = layout;
+  return p;
 }
 
 void *work_buffer(Plan *pl, int prec, int which, size_t bytes, hipStream_t s) {
@@ -389,10 +402,27 @@ void *work_buffer(Plan *pl, int prec, int which, size_t bytes, hipStream_t s) {
 
 template <typename T, typename TX>
 void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, int stop,
-                hipStream_t s, hipEvent_t *ev, bool full3d) {
+                hipStream_t s, hipEvent_t *ev, bool full3d, StageView *views) {
   auto mark = [&](int i) {
     if (ev) HIPCHECK(hipEventRecord(ev[i], s));
   };
+  // records where stage st left its output: plain view [F][A][Z] with strides
+  auto view = [&](int st, const void *p, int64_t A, int64_t Z, int64_t fs, int64_t as,
+                  int64_t zs) {
+    if (!views) return;
+    StageView &v = views[st];
+    v = StageView{};
+    v.p = p;
+    v.kind = 1;
+    v.F = 4 * (int64_t)nrhs;
+    v.A = A;
+    v.Z = Z;
+    v.fs = fs;
+    v.as = as;
+    v.zs = zs;
+  };
+  if (views)
+    for (int i = 0; i < AIM_NSTAGE; ++i) views[i] = StageView{};
   const HostPlan &h = md.hp;
   const int prec = sizeof(T) == 8 ? 0 : 1;
   const int Nx = h.grid[0], Ny = h.grid[1], Nz = h.grid[2];
@@ -409,7 +439,7 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     const int64_t A1 = (int64_t)Nx * Ny, V2 = (int64_t)Nx * Py;
     cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * A1, s);
     cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2, s);
-    cx<T> *gs = src_buffer<T>(pl, md, sizeof(cx<T>) * F * A1, s);
+    cx<T> *gs = src_buffer<T>(pl, md, sizeof(cx<T>) * F * A1, 2, s);
     mark(0);
     const int64_t no = md.n_plane_occ;
     if (no > 0) {
@@ -420,21 +450,25 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
       LAUNCHCHECK();
     }
     mark(1);
+    view(1, gs, Nx, Ny, A1, Ny, 1);
     if (stop <= 1) return;
     mark(2);
     fft_pass_contig(gs, g2, md.plan[1], Ny, Py, F * Nx, fftk::contig_map(Ny), fftk::contig_map(Py),
                     false, tw_of<T>(md, 1), s);
     mark(3);
+    view(3, g2, Nx, Py, V2, Py, 1);
     if (stop <= 3) return;
     fft_mid_pass(g2, md.plan[0], Nx, (int)F, Py, 1, md.H[0], md.H[1], 1, ghat2d_of<T>(md),
                  tw_of<T>(md, 0), 0, V2, s);
     mark(4);
+    view(4, g2, Nx, Py, V2, Py, 1);
     if (stop <= 4) return;
     // into the field-interleaved plane [Nx][Ny][F] the interpolation reads
     fft_pass_contig(g2, g0, md.plan[1], Py, Ny, F * Nx, fftk::fields_inner(F, (int64_t)Nx * Py, Py, 1),
                     fftk::fields_inner(F, 1, (int64_t)Ny * F, F), true, tw_of<T>(md, 1), s);
     mark(5);
     mark(6);
+    view(6, g0, Nx, Ny, 1, (int64_t)Ny * F, F);
     return;
   }
   if (thin_layout<T>(Pz)) {
@@ -445,7 +479,7 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * V0, s);
     cx<T> *g1 = (cx<T> *)work_buffer(pl, prec, 1, sizeof(cx<T>) * F * V1, s);
     cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2, s);
-    cx<T> *gs = src_buffer<T>(pl, md, sizeof(cx<T>) * F * V0, s);
+    cx<T> *gs = src_buffer<T>(pl, md, sizeof(cx<T>) * F * V0, 1, s);
     mark(0);
     if (md.n_occ > 0) {
       hipLaunchKernelGGL((k_anterp_gather<T, TX>),
@@ -455,22 +489,27 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
       LAUNCHCHECK();
     }
     mark(1);
+    view(1, gs, A1, Nz, V0, Nz, 1);
     if (stop <= 1) return;
     fft_pass_contig(gs, g1, md.plan[2], Nz, Pz, F * A1, fftk::contig_map(Nz),
                     fftk::contig_map(A1, V1, 1, A1), false, tw_of<T>(md, 2), s);
     mark(2);
+    view(2, g1, A1, Pz, V1, 1, A1);
     if (stop <= 2) return;
     fft_pass_contig(g1, g2, md.plan[1], Ny, Py, F * Pz * Nx, fftk::contig_map(Ny),
                     fftk::contig_map(Py), false, tw_of<T>(md, 1), s);
     mark(3);
+    view(3, g2, (int64_t)Nx * Py, Pz, V2, 1, (int64_t)Nx * Py);
     if (stop <= 3) return;
     fft_mid_pass(g2, md.plan[0], Nx, (int)F, Py, Pz, md.H[0], md.H[1], md.H[2], ghat_of<T>(md),
                  tw_of<T>(md, 0), 0, V2, s);
     mark(4);
+    view(4, g2, (int64_t)Nx * Py, Pz, V2, 1, (int64_t)Nx * Py);
     if (stop <= 4) return;
     fft_pass_contig(g2, g1, md.plan[1], Py, Ny, F * Pz * Nx, fftk::contig_map(Py),
                     fftk::contig_map(Ny), true, tw_of<T>(md, 1), s);
     mark(5);
+    view(5, g1, A1, Pz, V1, 1, A1);
     if (stop <= 5) return;
     if (full3d) {  // inspection: every line
       fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * A1, fftk::contig_map(A1, V1, 1, A1),
@@ -482,6 +521,7 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
                       fftk::fields_inner(F, V1, 1, A1, md.occ_lines, nl),
                       fftk::fields_inner(F, 1, (int64_t)Nz * F, F, md.occ_lines, nl), true,
                       tw_of<T>(md, 2), s);
+      view(6, g0, A1, Nz, 1, (int64_t)Nz * F, F);
     }
     mark(6);
     return;
@@ -504,7 +544,7 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
   if (stop <= 1 || !md.fuse_proj[prec] || nrhs > 1 ||
       !anterp_fftz(x, ldx, nrhs, md.node_ptr, md.ent_col, lamT_of<T>(md), Nz, (int64_t)Nx * Ny, g1,
                    Pzs, (int64_t)Nx * Ny * Pzs, tw_of<T>(md, 2), md.plan[2], s)) {
-    cx<T> *gs = src_buffer<T>(pl, md, sizeof(cx<T>) * F * V0, s);
+    cx<T> *gs = src_buffer<T>(pl, md, sizeof(cx<T>) * F * V0, 1, s);
     if (md.n_occ > 0) {
       hipLaunchKernelGGL((k_anterp_gather<T, TX>),
                          dim3((unsigned)((md.n_occ + 4 * npw - 1) / (4 * npw)), nrhs),
@@ -513,6 +553,7 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
       LAUNCHCHECK();
     }
     mark(1);
+    view(1, gs, (int64_t)Nx * Ny, Nz, V0, Nz, 1);
     if (stop <= 1) return;
     if (full3d) {  // inspection: every line, into g1
       fft_pass_contig(gs, g1, md.plan[2], Nz, Pz, F * Nx * Ny, fftk::contig_map(Nz),
@@ -529,19 +570,37 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     mark(1);
   }
   mark(2);
+  view(2, gz, (int64_t)Nx * Ny, Pz, (int64_t)Nx * Ny * Pzs, Pzs, 1);
   if (stop <= 2) return;
   // y passes: rows outside a plane's occupied y range are zero on input
   // (forward) and never read on output (inverse); inspection keeps every row
   const fftk::LineMap m1y = full3d ? m1 : fftk::with_range(m1, md.occ_yrange, Nx);
+  auto blocked_view = [&](int st) {
+    if (!views) return;
+    StageView &v = views[st];
+    v = StageView{};
+    v.p = g2;
+    v.kind = 2;
+    v.F = F;
+    v.A = (int64_t)Nx * Py;
+    v.Z = Pz;
+    v.Nx = Nx;
+    v.Py = Py;
+    v.blk = blk;
+    v.fstride = V2;
+  };
   fft_pass_strided(gz, g2, md.plan[1], Ny, Py, F * Nx, Pz, m1y, m2, false, tw_of<T>(md, 1), s);
   mark(3);
+  blocked_view(3);
   if (stop <= 3) return;
   fft_mid_pass(g2, md.plan[0], Nx, (int)F, Py, Pz, md.H[0], md.H[1], md.H[2], ghat_of<T>(md),
                tw_of<T>(md, 0), blk, V2, s);
   mark(4);
+  blocked_view(4);
   if (stop <= 4) return;
   fft_pass_strided(g2, g1, md.plan[1], Py, Ny, F * Nx, Pz, m2, m1y, true, tw_of<T>(md, 1), s);
   mark(5);
+  view(5, g1, (int64_t)Nx * Ny, Pz, (int64_t)Nx * Ny * Pzs, Pzs, 1);
   if (stop <= 5) return;
   if (full3d) {  // inspection: every line
     fft_pass_contig(g1, g0, md.plan[2], Pz, Nz, F * Nx * Ny, fftk::contig_map(Pzs),
@@ -554,6 +613,7 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
                     fftk::fields_inner(F, V1, Pzs, 1, md.occ_lines, nl),
                     fftk::fields_inner(F, 1, (int64_t)Nz * F, F, md.occ_lines, nl, md.occ_zrange),
                     true, tw_of<T>(md, 2), s);
+    view(6, g0, (int64_t)Nx * Ny, Nz, 1, (int64_t)Nz * F, F);
   }
   mark(6);
 }
@@ -638,6 +698,36 @@ void copy_far_stage(Plan *pl, MeshDev &md, int nrhs, int stage, void *out, hipSt
 template void copy_far_stage<double>(Plan *, MeshDev &, int, int, void *, hipStream_t);
 template void copy_far_stage<float>(Plan *, MeshDev &, int, int, void *, hipStream_t);
 
+namespace {
+// out[(f A + a) Z + z] = in[f fs + a as + z zs] (inspection)
+template <typename T>
+__global__ void k_view_copy(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, int64_t F,
+                            int64_t A, int64_t Z, int64_t fs, int64_t as, int64_t zs) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= F * A * Z) return;
+  const int64_t z = t % Z, a = (t / Z) % A, f = t / (Z * A);
+  out[t] = in[f * fs + a * as + z * zs];
+}
+}  // namespace
+
+template <typename T>
+void copy_stage_view(const StageView &v, void *out, hipStream_t s) {
+  const int64_t tot = v.F * v.A * v.Z;
+  const unsigned blocks = (unsigned)((tot + 255) / 256);
+  if (v.kind == 1) {
+    hipLaunchKernelGGL((k_view_copy<T>), dim3(blocks), dim3(256), 0, s, (const cx<T> *)v.p,
+                       (cx<T> *)out, v.F, v.A, v.Z, v.fs, v.as, v.zs);
+  } else if (v.kind == 2) {
+    hipLaunchKernelGGL((k_unblock<T>), dim3(blocks), dim3(256), 0, s, (const cx<T> *)v.p,
+                       (cx<T> *)out, v.F, v.Nx, v.Py, (int)v.Z, v.blk, v.fstride);
+  } else {
+    throw Error(AIM_ERR_ARG, "the product has no such stage for this mesh");
+  }
+  LAUNCHCHECK();
+}
+template void copy_stage_view<double>(const StageView &, void *, hipStream_t);
+template void copy_stage_view<float>(const StageView &, void *, hipStream_t);
+
 void autotune_mesh(Plan *pl, MeshDev &md, hipStream_t s) {
   const int64_t n = md.hp.n;
   hipEvent_t e0, e1;
@@ -707,11 +797,11 @@ void autotune_mesh(Plan *pl, MeshDev &md, hipStream_t s) {
 }
 
 template void far_stages<double, double>(Plan *, MeshDev &, int, const double2 *, int64_t, int,
-                                         hipStream_t, hipEvent_t *, bool);
+                                         hipStream_t, hipEvent_t *, bool, StageView *);
 template void far_stages<float, float>(Plan *, MeshDev &, int, const float2 *, int64_t, int,
-                                       hipStream_t, hipEvent_t *, bool);
+                                       hipStream_t, hipEvent_t *, bool, StageView *);
 template void far_stages<float, double>(Plan *, MeshDev &, int, const double2 *, int64_t, int,
-                                        hipStream_t, hipEvent_t *, bool);
+                                        hipStream_t, hipEvent_t *, bool, StageView *);
 template void matvec_mesh<double, double, double>(Plan *, MeshDev &, int, const double2 *, int64_t,
                                                   double2 *, int64_t, hipStream_t, hipEvent_t *);
 template void matvec_mesh<float, float, float>(Plan *, MeshDev &, int, const float2 *, int64_t,
