@@ -205,13 +205,17 @@ typedef struct {
  * directly instead. */
 #define AIM_SOLVE_NO_GRAPH 1
 
-/* Per right-hand side results of aim_gmres_solve. */
+/* Results of aim_gmres_solve for one system (one mesh lit by one wave).
+ * Every system of a call advances in lock-step through shared batched
+ * products, so the product counts and the time are those of the whole call;
+ * the iterations, residual and convergence are the system's own. */
 typedef struct {
-  int32_t iterations;      /* inner GMRES iterations */
-  int32_t converged;       /* 1 if the FP64 residual met tol */
-  int32_t matvec_low;      /* products in the requested precision */
-  int32_t matvec_fp64;     /* FP64 residual products */
-  double residual;         /* final ||b - A64 x|| / ||b|| */
+  int32_t iterations;      /* inner GMRES iterations this system took part in
+                              (summed over restarts and refinement steps) */
+  int32_t converged;       /* 1 if this system's FP64 residual met tol */
+  int32_t matvec_low;      /* batched products in the requested precision */
+  int32_t matvec_fp64;     /* batched FP64 residual products */
+  double residual;         /* this system's final ||b - A64 x|| / ||b|| */
   double seconds;          /* wall time of the whole solve call */
 } aim_solve_stats;
 
@@ -260,6 +264,16 @@ aim_status aim_matvec_timed(aim_plan *plan, aim_precision prec, int32_t nrhs, co
                             void *y, int32_t nrep, double *stage_ms, double *total_ms,
                             void *hip_stream);
 
+/* Measures the product as a HIP graph: runs one product directly (so that
+ * every work buffer exists), captures nrep products y = Z^AIM x back to back
+ * into one graph, launches it once untimed, then nlaunch times with HIP
+ * events around each launch, and synchronises. launch_ms (host, nlaunch
+ * doubles) receives each launch's event time for all nrep products. x, y as
+ * for aim_matvec_timed. */
+aim_status aim_matvec_graph_timed(aim_plan *plan, aim_precision prec, int32_t nrhs,
+                                  const void *x, void *y, int32_t nrep, int32_t nlaunch,
+                                  double *launch_ms, void *hip_stream);
+
 /* Solves Z^AIM x = b for nrhs_per_mesh plane waves on every mesh of the plan
  * (waves: host, nrhs_per_mesh entries, the same set for every mesh) with
  * restarted GMRES, right Jacobi preconditioning D = diag(Z^MOM), FP64
@@ -268,7 +282,8 @@ aim_status aim_matvec_timed(aim_plan *plan, aim_precision prec, int32_t nrhs, co
  * (at most 20 refinement steps; an inner solve ends at its target or where
  * the c64 operator's rounding stops its true residual from falling).
  * x_io: device c128 [n_total][nrhs_per_mesh]. stats: host
- * [nrhs_per_mesh] (per wave, worst over meshes) or NULL. Synchronises.
+ * [nmesh][nrhs_per_mesh] (entry mesh * nrhs_per_mesh + wave) or NULL.
+ * Synchronises.
  * Returns AIM_ERR_NOCONV if some right-hand side missed tol (x_io then holds
  * the last iterate). A zero right-hand side gives x = 0. */
 aim_status aim_gmres_solve(aim_plan *plan, aim_precision prec, int32_t nrhs_per_mesh,
@@ -335,6 +350,25 @@ aim_status aim_export(const aim_plan *plan, int32_t mesh, int32_t what, void *ho
  * stage: [4 nrhs] x {NxNyNz, NxNyPz, NxPyPz, NxPyPz, NxNyPz, NxNyNz}). */
 aim_status aim_debug_far_stage(aim_plan *plan, aim_precision prec, int32_t mesh, int32_t nrhs,
                                const void *x, int32_t stage, void *grid_out, void *hip_stream);
+
+/* Runs the product's own far passes for one precision (the pruned and, for
+ * a scatterer in one grid plane, in-plane passes that aim_matvec launches;
+ * asynchronous) and copies the grid left after `stage` to grid_out (device,
+ * same precision as x) in the plain layout [4 nrhs][A][Z]:
+ *   3-D path:   1 (A, Z) = (Nx Ny, Nz), 2 and 5 (Nx Ny, Pz), 3 and 4 (Nx Py, Pz),
+ *               6 (Nx Ny, Nz);
+ *   plane path: 1 and 6 (Nx, Ny), 3 and 4 (Nx, Py) (aim_info.planar_z >= 0; it
+ *               has no z passes, so stages 2 and 5 give AIM_ERR_ARG).
+ * The product computes only what its next step reads, so only these elements
+ * are defined: stages 1-4 all; stage 5 the rows y inside each plane x's range
+ * of occupied z lines (3-D path); stage 6 the occupied z lines over their
+ * occupied z range (3-D path), every element (plane path). A z line (x, y)
+ * is occupied when it holds a node with a non-zero projection (or curl)
+ * weight, and its occupied range runs from its first to its last such node.
+ * Stages 1-3 stop after that stage; stages 4-6 run the whole far part. */
+aim_status aim_debug_product_stage(aim_plan *plan, aim_precision prec, int32_t mesh,
+                                   int32_t nrhs, const void *x, int32_t stage, void *grid_out,
+                                   void *hip_stream);
 
 const char *aim_last_error(void);
 

@@ -43,9 +43,11 @@ AIM_NSETUP = 5
 SETUP_PHASES = ("host_plan", "projection", "green", "near_fill", "tune")
 
 EXPORTED = [
-    "aim_setup", "aim_plan_info", "aim_destroy", "aim_matvec", "aim_matvec_timed", "aim_gmres_solve",
+    "aim_setup", "aim_plan_info", "aim_destroy", "aim_matvec", "aim_matvec_timed",
+    "aim_matvec_graph_timed", "aim_gmres_solve",
     "aim_excitation", "aim_rcs", "aim_host_plan_build", "aim_host_plan_export",
-    "aim_host_plan_destroy", "aim_export", "aim_debug_far_stage", "aim_last_error",
+    "aim_host_plan_destroy", "aim_export", "aim_debug_far_stage", "aim_debug_product_stage",
+    "aim_last_error",
 ]
 
 
@@ -120,6 +122,8 @@ def lib():
         "aim_matvec": [P, c_int32, c_int32, P, P, P],
         "aim_matvec_timed": [P, c_int32, c_int32, P, P, c_int32, POINTER(c_double),
                              POINTER(c_double), P],
+        "aim_matvec_graph_timed": [P, c_int32, c_int32, P, P, c_int32, c_int32, POINTER(c_double),
+                                   P],
         "aim_gmres_solve": [P, c_int32, c_int32, POINTER(AimPlanewave), POINTER(AimSolveOpts), P,
                             POINTER(AimSolveStats), P],
         "aim_excitation": [P, c_int32, POINTER(AimPlanewave), P, P],
@@ -131,6 +135,7 @@ def lib():
                                  POINTER(c_int32), POINTER(c_int32), POINTER(c_double)],
         "aim_export": [P, c_int32, c_int32, P, c_size_t],
         "aim_debug_far_stage": [P, c_int32, c_int32, c_int32, P, c_int32, P, P],
+        "aim_debug_product_stage": [P, c_int32, c_int32, c_int32, P, c_int32, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -144,6 +149,34 @@ def lib():
     L.aim_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
+
+
+def check_vectors(x, y, n_total: int, dtype, device: int) -> int:
+    """Validates the vectors of a product before their pointers reach the
+    library, which writes nrhs * n_total elements of y: x (and y, if not
+    None) must be contiguous tensors of `dtype` on GPU `device`, of shape
+    (n_total,) or (nrhs, n_total), y of x's size. Returns nrhs."""
+    for name, t in (("x", x), ("y", y)):
+        if t is None:
+            continue
+        if t.dtype != dtype:
+            raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.dim() not in (1, 2) or t.shape[-1] != n_total or t.numel() == 0:
+            raise ValueError(f"{name} must have shape (n_total,) or (nrhs, n_total) with "
+                             f"n_total = {n_total}, got {tuple(t.shape)}")
+    if y is not None:
+        if y.numel() != x.numel():
+            raise ValueError(f"y holds {y.numel()} elements, x {x.numel()}")
+        xb, yb = x.data_ptr(), y.data_ptr()
+        nb = x.numel() * x.element_size()
+        if xb < yb + nb and yb < xb + nb:
+            raise ValueError("x and y must not overlap")
+    for name, t in (("x", x), ("y", y)):
+        if t is not None and (not t.is_cuda or t.device.index != device):
+            raise ValueError(f"{name} must be on cuda:{device}, got {t.device}")
+    return x.numel() // n_total
 
 
 def _check(status: int):
@@ -301,29 +334,45 @@ class Plan:
 
     def matvec(self, x, precision=AIM_FP64, out=None, stream=None):
         """y = Z x for x of shape (n_total,) or (nrhs, n_total): complex128 for
-        AIM_FP64 and AIM_MIXED_IO64, complex64 for AIM_MIXED (device tensors)."""
+        AIM_FP64 and AIM_MIXED_IO64, complex64 for AIM_MIXED (device tensors
+        on the plan's GPU). `out`, if given, receives y and must match x."""
         torch = self._torch
         dt = torch.complex64 if precision == AIM_MIXED else torch.complex128
-        if x.dtype != dt or not x.is_cuda:
-            raise ValueError(f"x must be a {dt} device tensor")
-        xx = x.reshape(-1, self.n_total)
-        if not xx.is_contiguous():
-            raise ValueError("x must be contiguous")
-        y = out if out is not None else torch.empty_like(xx)
-        _check(lib().aim_matvec(self._h, precision, xx.shape[0], c_void_p(xx.data_ptr()),
+        nrhs = check_vectors(x, out, self.n_total, dt, self.device)
+        xx = x.reshape(nrhs, self.n_total)
+        y = out.reshape(nrhs, self.n_total) if out is not None else torch.empty_like(xx)
+        _check(lib().aim_matvec(self._h, precision, nrhs, c_void_p(xx.data_ptr()),
                                 c_void_p(y.data_ptr()), self._stream(stream)))
         return y.reshape(x.shape)
 
     def matvec_timed(self, x, y, precision, nrep, stream=None):
         """nrep products with HIP events between the kernels; returns
         (per-stage summed ms (AIM_NSTAGE,), first-to-last event ms)."""
+        torch = self._torch
+        dt = torch.complex64 if precision == AIM_MIXED else torch.complex128
+        if y is None:
+            raise ValueError("y is required")
+        nrhs = check_vectors(x, y, self.n_total, dt, self.device)
         st = (c_double * AIM_NSTAGE)()
         tot = c_double()
-        nrhs = x.numel() // self.n_total
         _check(lib().aim_matvec_timed(self._h, precision, nrhs, c_void_p(x.data_ptr()),
                                       c_void_p(y.data_ptr()), int(nrep), st, ctypes.byref(tot),
                                       self._stream(stream)))
         return np.array(st[:]), tot.value
+
+    def matvec_graph_timed(self, x, y, precision, nrep, nlaunch=5, stream=None):
+        """nrep products captured in one HIP graph, launched nlaunch times with
+        events around each launch: returns the per-launch ms (nlaunch,)."""
+        torch = self._torch
+        dt = torch.complex64 if precision == AIM_MIXED else torch.complex128
+        if y is None:
+            raise ValueError("y is required")
+        nrhs = check_vectors(x, y, self.n_total, dt, self.device)
+        ms = (c_double * int(nlaunch))()
+        _check(lib().aim_matvec_graph_timed(self._h, precision, nrhs, c_void_p(x.data_ptr()),
+                                            c_void_p(y.data_ptr()), int(nrep), int(nlaunch), ms,
+                                            self._stream(stream)))
+        return np.array(ms[:])
 
     def excitation(self, waves, stream=None):
         torch = self._torch
@@ -344,13 +393,14 @@ class Plan:
             x = torch.zeros((R, self.n_total), dtype=torch.complex128, device="cuda")
         opts = AimSolveOpts(float(tol), int(restart), int(max_iter), 1 if x0 is not None else 0,
                             0 if graphs else AIM_SOLVE_NO_GRAPH)
-        st = (AimSolveStats * R)()
+        st = (AimSolveStats * (self.nmesh * R))()
         status = lib().aim_gmres_solve(self._h, precision, R, arr, ctypes.byref(opts),
                                        c_void_p(x.data_ptr()), st, self._stream(stream))
         if status != AIM_OK and (status != AIM_ERR_NOCONV or raise_on_noconv):
             _check(status)
-        stats = [dict(iterations=s.iterations, converged=bool(s.converged), matvec_low=s.matvec_low,
-                      matvec_fp64=s.matvec_fp64, residual=s.residual, seconds=s.seconds) for s in st]
+        stats = [dict(mesh=i // R, wave=i % R, iterations=s.iterations, converged=bool(s.converged),
+                      matvec_low=s.matvec_low, matvec_fp64=s.matvec_fp64, residual=s.residual,
+                      seconds=s.seconds) for i, s in enumerate(st)]
         return x, stats
 
     def rcs(self, x, theta, phi, stream=None):
@@ -401,4 +451,28 @@ class Plan:
         out = torch.empty((R, 4) + shapes[stage], dtype=dt, device="cuda")
         _check(lib().aim_debug_far_stage(self._h, precision, mesh, R, c_void_p(xx.data_ptr()), stage,
                                          c_void_p(out.data_ptr()), self._stream(stream)))
+        return out
+
+    def product_stage(self, mesh: int, x, stage: int, precision=AIM_FP64, stream=None):
+        """The grid the product's own (pruned / in-plane) passes leave after
+        `stage`, in the plain layout (nrhs, 4, A, Z) of aim_debug_product_stage;
+        only the elements that header names are defined."""
+        torch = self._torch
+        inf = self._info
+        Nx, Ny, Nz = inf["grid"][mesh]
+        Px, Py, Pz = inf["pad"][mesh]
+        if inf["planar_z"][mesh] >= 0:
+            shapes = {1: (Nx, Ny), 3: (Nx, Py), 4: (Nx, Py), 6: (Nx, Ny)}
+        else:
+            shapes = {1: (Nx * Ny, Nz), 2: (Nx * Ny, Pz), 3: (Nx * Py, Pz), 4: (Nx * Py, Pz),
+                      5: (Nx * Ny, Pz), 6: (Nx * Ny, Nz)}
+        if stage not in shapes:
+            raise ValueError(f"the product has no stage {stage} for mesh {mesh}")
+        dt = torch.complex128 if precision == AIM_FP64 else torch.complex64
+        xx = x.reshape(-1, self.n_total).to(dt).contiguous()
+        R = xx.shape[0]
+        out = torch.empty((R, 4) + shapes[stage], dtype=dt, device="cuda")
+        _check(lib().aim_debug_product_stage(self._h, precision, mesh, R, c_void_p(xx.data_ptr()),
+                                             stage, c_void_p(out.data_ptr()),
+                                             self._stream(stream)))
         return out

@@ -37,6 +37,11 @@ void *dev_alloc(Plan *pl, size_t bytes) {
 
 void dev_free(Plan *pl, void *p) {
   if (!p) return;
+  // The buffer may still be read by kernels on any stream the library used
+  // (the caller's or the solver's), while the allocator may hand it out again
+  // at once on the stream it was obtained on: finish all work first. Frees
+  // happen on growth, at the end of a solve or RCS call and at destroy only.
+  HIPCHECK(hipDeviceSynchronize());
   for (size_t i = 0; i < pl->live.size(); ++i)
     if (pl->live[i].first == p) {
       pl->device_bytes -= (double)pl->live[i].second;
@@ -51,7 +56,7 @@ void dev_free(Plan *pl, void *p) {
 
 static void free_all(Plan *pl) {
   if (!pl) return;
-  if (pl->own_alloc) (void)hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();  // no kernel may still read what is freed
   for (auto &a : pl->live) {
     if (pl->own_alloc)
       (void)hipFree(a.first);
@@ -332,6 +337,56 @@ aim_status aim_matvec_timed(aim_plan *plan, aim_precision prec, int32_t nrhs, co
   return r;
 }
 
+aim_status aim_matvec_graph_timed(aim_plan *plan, aim_precision prec, int32_t nrhs, const void *x,
+                                  void *y, int32_t nrep, int32_t nlaunch, double *launch_ms,
+                                  void *hip_stream) {
+  aim_status st = matvec_check(plan, prec, nrhs, x, y);
+  if (st != AIM_OK) return st;
+  if (nrep < 1 || nlaunch < 1 || !launch_ms) return fail(AIM_ERR_ARG, "bad repetition arguments");
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipStream_t cs = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ex = nullptr;
+  aim_status r = guarded([&] {
+    // one direct product first: work buffers exist before the capture
+    matvec_all(plan, prec, nrhs, x, y, s, nullptr);
+    HIPCHECK(hipStreamSynchronize(s));
+    HIPCHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    HIPCHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    try {
+      for (int i = 0; i < nrep; ++i) matvec_all(plan, prec, nrhs, x, y, cs, nullptr);
+    } catch (...) {
+      (void)hipStreamEndCapture(cs, &g);
+      throw;
+    }
+    HIPCHECK(hipStreamEndCapture(cs, &g));
+    HIPCHECK(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    HIPCHECK(hipGraphLaunch(ex, cs));  // first launch uploads the graph (untimed)
+    HIPCHECK(hipStreamSynchronize(cs));
+    for (int l = 0; l < nlaunch; ++l) {
+      HIPCHECK(hipEventRecord(e0, cs));
+      HIPCHECK(hipGraphLaunch(ex, cs));
+      HIPCHECK(hipEventRecord(e1, cs));
+      HIPCHECK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+      launch_ms[l] = ms;
+    }
+  });
+  if (ex) (void)hipGraphExecDestroy(ex);
+  if (g) (void)hipGraphDestroy(g);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (cs) {
+    (void)hipStreamSynchronize(cs);
+    (void)hipStreamDestroy(cs);
+  }
+  return r;
+}
+
 aim_status aim_excitation(aim_plan *plan, int32_t nwaves, const aim_planewave *waves, void *b,
                           void *hip_stream) {
   if (!plan || !waves || !b || nwaves < 1) return fail(AIM_ERR_ARG, "bad argument");
@@ -429,6 +484,34 @@ aim_status aim_debug_far_stage(aim_plan *plan, aim_precision prec, int32_t mesh,
       far_stages<float, float>(plan, md, nrhs, (const float2 *)x + md.offset, plan->n_total, stage,
                                s, nullptr, true);
       copy_far_stage<float>(plan, md, nrhs, stage, grid_out, s);
+    }
+  });
+}
+
+aim_status aim_debug_product_stage(aim_plan *plan, aim_precision prec, int32_t mesh, int32_t nrhs,
+                                   const void *x, int32_t stage, void *grid_out,
+                                   void *hip_stream) {
+  if (!plan || !x || !grid_out || mesh < 0 || mesh >= plan->nmesh || nrhs < 1 || stage < 1 ||
+      stage > 6)
+    return fail(AIM_ERR_ARG, "bad argument");
+  if (prec != AIM_FP64 && prec != AIM_MIXED) return fail(AIM_ERR_ARG, "bad precision");
+  if (prec == AIM_MIXED && !plan->mixed) return fail(AIM_ERR_STATE, "plan has no FP32 data");
+  hipStream_t s = (hipStream_t)hip_stream;
+  return guarded([&] {
+    MeshDev &md = plan->mesh[mesh];
+    // stages 1-3 stop there (the x pass overwrites stage 3's grid in place);
+    // stages 4-6 run the product's whole far part, whose later passes leave
+    // those grids in place
+    const int stop = stage <= 3 ? stage : 6;
+    StageView v[AIM_NSTAGE];
+    if (prec == AIM_FP64) {
+      far_stages<double, double>(plan, md, nrhs, (const double2 *)x + md.offset, plan->n_total,
+                                 stop, s, nullptr, false, v);
+      copy_stage_view<double>(v[stage], grid_out, s);
+    } else {
+      far_stages<float, float>(plan, md, nrhs, (const float2 *)x + md.offset, plan->n_total, stop,
+                               s, nullptr, false, v);
+      copy_stage_view<float>(v[stage], grid_out, s);
     }
   });
 }

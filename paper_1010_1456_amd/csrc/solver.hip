@@ -780,21 +780,17 @@ aim_status gmres_solve(Plan *pl, aim_precision prec, int R, const aim_planewave 
       double rel = b2[i] > 0 ? std::sqrt(r2[i] / b2[i]) : 0.0;
       if (!(rel <= tol)) all_ok = false;
     }
-    if (st) {
-      for (int w = 0; w < R; ++w) {
+    if (st) {  // one entry per system (mesh, wave), mesh-major
+      for (int sidx = 0; sidx < S; ++sidx) {
         aim_solve_stats q{};
-        q.converged = 1;
-        for (int mi = 0; mi < pl->nmesh; ++mi) {
-          const int sidx = mi * R + w;
-          double rel = b2[sidx] > 0 ? std::sqrt(r2[sidx] / b2[sidx]) : 0.0;
-          q.iterations = std::max(q.iterations, its[sidx]);
-          q.residual = std::max(q.residual, rel);
-          if (!(rel <= tol)) q.converged = 0;
-        }
+        const double rel = b2[sidx] > 0 ? std::sqrt(r2[sidx] / b2[sidx]) : 0.0;
+        q.iterations = its[sidx];
+        q.residual = rel;
+        q.converged = rel <= tol ? 1 : 0;
         q.matvec_low = n_low;
         q.matvec_fp64 = n64;
         q.seconds = secs;
-        st[w] = q;
+        st[sidx] = q;
       }
     }
     result = all_ok ? AIM_OK : AIM_ERR_NOCONV;

@@ -184,3 +184,28 @@ def test_grid_size_limits():
         lib_aim.host_plan(square(180.0), tris, 0.3e9)
     assert e.value.status == lib_aim.AIM_ERR_ARG
     assert "largest supported FFT length" in str(e.value)
+
+
+def test_binding_rejects_bad_product_vectors():
+    """The binding checks x and y before their pointers reach the library
+    (which writes nrhs * n_total elements of y): dtype, contiguity, shape,
+    size, overlap and device."""
+    torch = pytest.importorskip("torch")
+    n, dt = 10, torch.complex128
+    x = torch.zeros((2, n), dtype=dt)
+    cases = [
+        (x.to(torch.complex64), None, "must be torch.complex128"),
+        (torch.zeros((n, 2), dtype=dt).t(), None, "contiguous"),
+        (torch.zeros((2, n + 1), dtype=dt), None, "shape"),
+        (torch.zeros((2, 2, n), dtype=dt), None, "shape"),
+        (torch.zeros((0, n), dtype=dt), None, "shape"),
+        (x, torch.zeros((3, n), dtype=dt), "elements"),
+        (x, torch.zeros((2, n), dtype=torch.complex64), "must be torch.complex128"),
+        (x, x, "overlap"),
+        (x[0], x[0:1].reshape(n), "overlap"),
+        (x, torch.zeros((2, n), dtype=dt), "must be on cuda:0"),
+        (x, None, "must be on cuda:0"),
+    ]
+    for xx, yy, msg in cases:
+        with pytest.raises(ValueError, match=msg):
+            lib_aim.check_vectors(xx, yy, n, dt, 0)
