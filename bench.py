@@ -5,10 +5,13 @@ A step is one AIM product y = Z x of the hot path: precision staging of the
 c128 solver vector, projection, pruned forward FFT passes, the x pass with the
 Green's spectrum multiply, pruned inverse passes, interpolation fused with the
 near-zone correction. The headline is the mixed path (c64 arithmetic on c128
-vectors, as the solver applies it) on the 8-lambda PEC sphere; the FP64 path
-is timed on the same input beside it. Per-kernel durations come from HIP events
-recorded between the kernels of every timed product. The FP64 CPU oracle is
-timed on a bounded sample on the host for reference.
+vectors, as the solver applies it) on the 8-lambda PEC sphere with the paper's
+formulation for closed bodies, the combined-field equation with alpha = 0.6
+(the EFIE operator is timed beside it as a reference line); the FP64 path
+is timed on the same input beside it. The rate comes from HIP events around a
+HIP graph of K products (median of several launches); per-kernel durations from
+HIP events recorded between the kernels of a second pass of K products. The
+FP64 CPU oracle's product is timed on the host cores for reference.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere8]
 """
@@ -216,21 +219,74 @@ def cpu_fill_baseline(cfg, freq_hz):
                        f"entries, M={cfg['order']}) by oracle.mom.sparse_z and oracle.aim.zgrid_entries")}
 
 
-def time_path(plan, A, prec, x, y, steps, warmup):
+def time_path(plan, A, prec, x, y, steps, warmup, launches):
+    """The product timed as a HIP graph of `steps` products, launched
+    `launches` times with events around each launch (median reported), and a
+    second pass of `steps` direct products with events between the kernels
+    for the per-step times. Returns (graph ms per launch, stage ms per
+    product, wall seconds around the graph launches)."""
     import torch
 
-    if warmup > 0:
-        plan.matvec_timed(x, y, prec, warmup)
+    for _ in range(warmup):
+        plan.matvec(x, prec, out=y)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stage_ms, total_ms = plan.matvec_timed(x, y, prec, steps)
+    launch_ms = plan.matvec_graph_timed(x, y, prec, steps, launches)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return wall, stage_ms / steps, total_ms
+    stage_ms, _ = plan.matvec_timed(x, y, prec, steps)
+    torch.cuda.synchronize()
+    return launch_ms, stage_ms / steps, wall
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """HBM bandwidth of a plain device-to-device copy of nbytes (read + write
+    counted), median of reps timed copies after one warm-up: the measured
+    ceiling the product's kernels are also compared with."""
+    import torch
+
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        out.append(2 * nbytes / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del a, b
+    return float(np.median(out))
+
+
+def host_cpu():
+    """(cores this process may run on, CPU model name)."""
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp and omp.isdigit():
+        cores = min(cores, int(omp))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return max(1, cores), model
 
 
 def cpu_baseline(mesh, cfg, nrhs, pad, cfie_alpha=None):
-    """The FP64 oracle's FFT-form product on the host cores (one product)."""
+    """The FP64 oracle's FFT-form product (oracle.aim.matvec_fft) on the host:
+    on every core available to the process (median of 5 after one warm-up),
+    and on one thread (one product after the warm-up)."""
     import scipy.fft
     import scipy.sparse
 
@@ -239,7 +295,7 @@ def cpu_baseline(mesh, cfg, nrhs, pad, cfie_alpha=None):
     from oracle.rwg import build_rwg
     from workloads import random_current
 
-    cores = max(1, min(16, os.cpu_count() or 1))
+    cores, model = host_cpu()
     k = wavenumber(mesh.freq_hz)
     t_setup = time.perf_counter()
     rwg = build_rwg(mesh.verts, mesh.tris)
@@ -254,29 +310,64 @@ def cpu_baseline(mesh, cfg, nrhs, pad, cfie_alpha=None):
     if cfie_alpha is not None:
         op.curl = oaim.curl_projection(rwg, grid, anc)
         op.alpha = cfie_alpha
+    x = random_current(rwg.n, nrhs=nrhs, seed=7)
     with scipy.fft.set_workers(cores):
         ghat = oaim.green_spectrum(k, grid, pad)
-        log(f"[cpu_baseline] oracle set-up {time.perf_counter() - t_setup:.1f} s")
-        x = random_current(rwg.n, nrhs=nrhs, seed=7)
+        log(f"[cpu_baseline] oracle set-up {time.perf_counter() - t_setup:.1f} s, {cores} cores")
+        oaim.matvec_fft(op, x, pad=pad, ghat=ghat)  # warm-up
+        times = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            oaim.matvec_fft(op, x, pad=pad, ghat=ghat)
+            times.append(time.perf_counter() - t0)
+    with scipy.fft.set_workers(1):
         t0 = time.perf_counter()
         oaim.matvec_fft(op, x, pad=pad, ghat=ghat)
-        dt = time.perf_counter() - t0
+        t1 = time.perf_counter() - t0
+    dt = float(np.median(times))
     return {
-        "value": 1.0 / dt, "unit": "matvec/s", "cores": cores, "kind": "oracle",
-        "seconds_per_matvec": dt,
-        "sample": (f"one FP64 FFT-form AIM product (oracle.aim.matvec_fft) on the full workload "
-                   f"(N={rwg.n}, grid {tuple(int(v) for v in grid.n)} padded {tuple(pad)}), "
-                   f"scipy.fft with {cores} workers; near-zone values set to 1 on the oracle's "
-                   f"own near pattern ({indices.shape[0]} nnz; the sparse product's cost does not "
-                   f"depend on the values)"),
+        "value": nrhs / dt, "unit": "matvec/s", "cores": cores, "kind": "oracle",
+        "cpu_model": model, "os_cpu_count": os.cpu_count(),
+        "seconds_per_matvec": dt, "seconds_per_matvec_runs": times,
+        "one_thread": {"value": nrhs / t1, "seconds_per_matvec": t1},
+        "sample": (f"the whole workload, not sampled: FP64 FFT-form AIM product "
+                   f"(oracle.aim.matvec_fft) with N={rwg.n}, grid {tuple(int(v) for v in grid.n)} "
+                   f"padded {tuple(pad)}, {nrhs} right-hand side(s); scipy.fft and BLAS on {cores} "
+                   f"threads, median of 5 after one warm-up; the one-thread figure is one product "
+                   f"after the warm-up. Near-zone values are 1 on the oracle's own near pattern "
+                   f"({indices.shape[0]} nnz): the sparse product's cost does not depend on them, "
+                   f"and the oracle's fill of the true values takes about an hour"),
     }
 
 
-def solve_compare(plan, A, mesh, workload, iters):
-    """The x-polarised wave toward -z solved by both paths (GMRES(100), Jacobi,
-    tol 1e-4, fixed iteration budget): time per iteration, residuals, and the
-    RCS agreement err_tt(mixed, fp64) on a 2-degree grid; for spheres also
-    err_tt against the Mie series."""
+def oracle_fixture(workload):
+    """(sigma_tt, metadata) the oracle wrote for this workload's
+    normal-incidence solve (tests/golden), or None."""
+    import gzip
+
+    path = os.path.join(ROOT, "tests", "golden", f"rcs_{workload}.txt.gz")
+    if not os.path.exists(path):
+        return None
+    meta = {}
+    with gzip.open(path, "rt") as f:
+        for line in f:
+            if not line.startswith("#"):
+                break
+            if ":=" in line:
+                k, v = line[1:].split(":=", 1)
+                v = v.strip()
+                if v.startswith("np.float64(") and v.endswith(")"):  # numpy scalar repr
+                    v = v[len("np.float64("):-1]
+                meta[k.strip()] = v
+    return np.loadtxt(path), meta
+
+
+def solve_compare(plan, A, mesh, workload, iters, alpha):
+    """The workload's plane waves solved by both paths (GMRES(100), Jacobi,
+    tol 1e-4 on the FP64 residual, at most `iters` iterations): time, systems
+    solved per second, iterations, residuals, and the RCS agreement
+    err_tt(mixed, fp64) on a 2-degree grid; against the oracle's solve where
+    a stored oracle RCS exists, and for spheres against the Mie series."""
     import torch
 
     from oracle import farfield as off
@@ -289,6 +380,7 @@ def solve_compare(plan, A, mesh, workload, iters):
     for prec in (A.AIM_MIXED, A.AIM_FP64):  # warm-up: work buffers, first launches
         plan.solve(waves, prec, tol=1e-4, restart=100, max_iter=2, raise_on_noconv=False)
     res = {}
+    nsys = plan.nmesh * len(waves)
     for name, prec in (("mixed", A.AIM_MIXED), ("fp64", A.AIM_FP64)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -296,22 +388,40 @@ def solve_compare(plan, A, mesh, workload, iters):
                            raise_on_noconv=False)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        sig = plan.rcs(x, th, ph)[:, 0]  # first wave, every scatterer
-        res[name] = dict(seconds=dt, iterations=st[0]["iterations"], residual=st[0]["residual"],
-                         converged=st[0]["converged"], matvec_low=st[0]["matvec_low"],
-                         matvec_fp64=st[0]["matvec_fp64"], ms_per_iteration=dt / max(1, st[0]["iterations"]) * 1e3,
-                         sigma=sig)
-        log(f"[bench] solve {name}: {st[0]['iterations']} its, residual {st[0]['residual']:.3e}, {dt:.2f} s")
+        sig = plan.rcs(x, th, ph)  # (mesh, wave, theta, phi)
+        its = [q["iterations"] for q in st]
+        conv = all(q["converged"] for q in st)
+        res[name] = dict(seconds=dt, systems=nsys, systems_per_s=nsys / dt,
+                         iterations=max(its), converged=conv,
+                         residual=max(q["residual"] for q in st),
+                         matvec_low=st[0]["matvec_low"], matvec_fp64=st[0]["matvec_fp64"],
+                         ms_per_iteration=dt / max(1, max(its)) * 1e3, sigma=sig)
+        if nsys > 1:
+            res[name]["per_mesh"] = [
+                dict(mesh=mi, max_iterations=max(q["iterations"] for q in st if q["mesh"] == mi),
+                     max_residual=max(q["residual"] for q in st if q["mesh"] == mi),
+                     converged=all(q["converged"] for q in st if q["mesh"] == mi))
+                for mi in range(plan.nmesh)]
+        log(f"[bench] solve {name}: {max(its)} its, worst residual {res[name]['residual']:.3e}, "
+            f"{'converged' if conv else 'NOT converged'}, {dt:.2f} s")
     out = {k: {kk: vv for kk, vv in v.items() if kk != "sigma"} for k, v in res.items()}
-    out["err_tt_mixed_vs_fp64"] = max(off.err_tt(a, b, th)
-                                      for a, b in zip(res["mixed"]["sigma"], res["fp64"]["sigma"]))
+    out["err_tt_mixed_vs_fp64"] = max(
+        off.err_tt(a, b, th) for a, b in zip(res["mixed"]["sigma"].reshape(-1, *th.shape, *ph.shape),
+                                             res["fp64"]["sigma"].reshape(-1, *th.shape, *ph.shape)))
+    fx = oracle_fixture(workload) if nsys == 1 else None
+    if fx is not None:
+        for name in ("mixed", "fp64"):
+            out[name]["err_tt_vs_oracle"] = off.err_tt(res[name]["sigma"][0, 0], fx[0], th)
+        out["oracle"] = {k: fx[1][k] for k in ("oracle_tol", "oracle_iterations",
+                                                "oracle_residual", "cfie_alpha")}
     if workload.startswith("sphere"):
         k = wavenumber(mesh.freq_hz)
         sm = omie.sigma_tt(k, float(workload[len("sphere"):]) * mesh.lam, th, ph)
         for name in ("mixed", "fp64"):
-            out[name]["err_tt_vs_mie"] = off.err_tt(res[name]["sigma"][0], sm, th)
-    out["mixed_speedup_per_iteration"] = res["fp64"]["ms_per_iteration"] / res["mixed"]["ms_per_iteration"]
-    out["setting"] = (f"GMRES(100), right Jacobi, tol 1e-4, at most {iters} iterations, "
+            out[name]["err_tt_vs_mie"] = off.err_tt(res[name]["sigma"][0, 0], sm, th)
+    out["mixed_speedup"] = res["fp64"]["seconds"] / res["mixed"]["seconds"]
+    out["setting"] = (("EFIE" if alpha is None else f"CFIE alpha {alpha} on closed scatterers, EFIE on "
+                       "open ones") + f"; GMRES(100), right Jacobi, tol 1e-4, at most {iters} iterations, "
                       + ("16 plane waves per scatterer (theta_i = i pi/7, both polarisations)"
                          if workload == "batch6" else "x-pol wave toward -z"))
     return out
@@ -392,24 +502,55 @@ def accuracy_sweep(A, max_iter):
     return out
 
 
+WORKLOAD_TEXT = {
+    "sphere8": "PEC sphere radius 8 lambda at 2.4 GHz, geodesic mesh nf=87 (151,380 triangles)",
+    "plate16": "PEC plate 16 lambda at 4.8 GHz, 144x144 squares (41,472 triangles)",
+    "plate1": "PEC plate 1 lambda at 0.3 GHz, 9x9 squares (162 triangles)",
+    "plate128": "PEC plate 128 lambda at 38.4 GHz, 1152x1152 squares",
+    "batch6": "6 scatterers in one plan at 0.3 GHz: PEC plates 2, 4, 8 lambda and spheres 1, 2, 4 "
+              "lambda (seeded vertex jitter), R right-hand sides each",
+}
+
+
+def measure_plan(plan, A, info, R, x, y, steps, warmup, launches):
+    """Graph-timed throughput, per-step times and byte models of both paths."""
+    res = {}
+    for name, prec, sg, sr, path in (("mixed", A.AIM_MIXED_IO64, 8, 4, 1),
+                                     ("fp64", A.AIM_FP64, 16, 8, 0)):
+        log(f"[bench] timing {name}: {warmup} warm-up, {launches} graph launches of {steps} products")
+        launch_ms, st_ms, wall = time_path(plan, A, prec, x, y, steps, warmup, launches)
+        b = sum(stage_bytes(info, mi, R, sg, sr, 16, 16, path) for mi in range(info["nmesh"]))
+        med = float(np.median(launch_ms))
+        res[name] = dict(launch_ms=launch_ms, ms_per_step=med / steps, stage_ms=st_ms, bytes=b,
+                         wall=wall, value=R * steps / (med * 1e-3))
+        log(f"[bench] {name}: {med / steps:.4f} ms/product (graph, median of {launches}; launches "
+            + ",".join(f"{v / steps:.4f}" for v in launch_ms) + "), stages(ms)="
+            + ",".join(f"{v:.3f}" for v in st_ms))
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--launches", type=int, default=5,
+                    help="graph launches of --steps products each; the median is reported")
     ap.add_argument("--workload", default="sphere8",
                     choices=["sphere8", "plate16", "plate1", "plate128", "batch6"])
     ap.add_argument("--nrhs", type=int, default=None,
                     help="right-hand sides per scatterer (default 1; 16 for batch6)")
     ap.add_argument("--order", type=int, default=None,
                     help="stencil order M (default: the workload's, 2)")
-    ap.add_argument("--cfie", type=float, default=None, metavar="ALPHA",
-                    help="solve the combined-field equation alpha EFIE + (1 - alpha) eta MFIE "
-                         "on the closed scatterers (the paper's alpha is 0.6; open ones keep "
-                         "the EFIE) instead of the EFIE")
+    ap.add_argument("--cfie", type=float, default=0.6, metavar="ALPHA",
+                    help="combination parameter of the combined-field equation alpha EFIE + "
+                         "(1 - alpha) eta MFIE on the closed scatterers (the paper's is 0.6); "
+                         "open ones keep the EFIE")
+    ap.add_argument("--efie", action="store_true",
+                    help="the EFIE on every scatterer (closed ones too)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--solve-iters", type=int, default=300,
-                    help="GMRES iteration budget of the solve comparison (0 skips it)")
+    ap.add_argument("--solve-iters", type=int, default=3000,
+                    help="GMRES iteration cap of the solve comparison (0 skips it)")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run a plain elementwise copy of 256 MiB (3 launches) whose "
                          "FETCH_SIZE/WRITE_SIZE counters calibrate the HBM byte counts")
@@ -433,7 +574,7 @@ def main(argv=None):
     import torch
 
     from paper_1010_1456_amd import aim as A
-    from workloads import CONFIGS, config_mesh, config_meshes, random_current
+    from workloads import CONFIGS, config_meshes, random_current
 
     if args.sweep:
         print(json.dumps(accuracy_sweep(A, 3000)), flush=True)
@@ -445,6 +586,7 @@ def main(argv=None):
             torch.mul(a, 1.0, out=b)  # reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
         del a, b
+    alpha = None if args.efie else args.cfie
     cfg = dict(CONFIGS[args.workload])
     if args.order is not None:
         cfg["order"] = args.order
@@ -452,65 +594,60 @@ def main(argv=None):
     meshes = config_meshes(args.workload)
     mesh = meshes[0]
     torch.cuda.set_device(0)
-    t0 = time.perf_counter()
-    plan = A.Plan([(m.verts, m.tris, m.freq_hz) for m in meshes], h_lambda=cfg["h_lambda"],
-                  order=cfg["order"], near_radius_lambda=cfg["near_radius_lambda"],
-                  cfie_alpha=args.cfie, cfie_closed_only=True)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
+    copy_gbs = copy_bandwidth()
+    log(f"[bench] device-to-device copy: {copy_gbs:.0f} GB/s")
+
+    def make_plan(a):
+        t0 = time.perf_counter()
+        pl = A.Plan([(m.verts, m.tris, m.freq_hz) for m in meshes], h_lambda=cfg["h_lambda"],
+                    order=cfg["order"], near_radius_lambda=cfg["near_radius_lambda"],
+                    cfie_alpha=a, cfie_closed_only=True)
+        torch.cuda.synchronize()
+        return pl, time.perf_counter() - t0
+
+    plan, setup_s = make_plan(alpha)
     info = plan.info()
     n = info["n_total"]
     log(f"[bench] set-up {setup_s:.2f} s: N={n} grid={info['grid'][0]} pad={info['pad'][0]} "
-        f"nnz={info['nnz_total']}")
+        f"nnz={info['nnz_total']} cfie={info['cfie_alpha']}")
     R = args.nrhs if args.nrhs is not None else (16 if args.workload == "batch6" else 1)
     x = torch.from_numpy(random_current(n, nrhs=R, seed=7)).cuda()
     y = torch.empty_like(x)
-
-    res = {}
-    for name, prec, sg, sr, path in (("mixed", A.AIM_MIXED_IO64, 8, 4, 1), ("fp64", A.AIM_FP64, 16, 8, 0)):
-        log(f"[bench] timing {name}: {args.warmup} warm-up + {args.steps} products")
-        wall, st_ms, tot_ms = time_path(plan, A, prec, x, y, args.steps, args.warmup)
-        b = sum(stage_bytes(info, mi, R, sg, sr, 16, 16, path) for mi in range(info["nmesh"]))
-        res[name] = dict(wall=wall, stage_ms=st_ms, total_ms=tot_ms, bytes=b)
-        log(f"[bench] {name}: {wall / args.steps * 1e3:.3f} ms/product, stages(ms)="
-            + ",".join(f"{v:.3f}" for v in st_ms))
+    res = measure_plan(plan, A, info, R, x, y, args.steps, args.warmup, args.launches)
 
     mx = res["mixed"]
     fused = bool(info["fused_projection"][0][1])  # (first scatterer's variant names the kernel)
-    ms_per_step = mx["wall"] / args.steps * 1e3
-    value = R * args.steps / mx["wall"]
     d = int(np.argmax(mx["stage_ms"]))
     achieved = mx["bytes"][d] / (mx["stage_ms"][d] * 1e-3) / 1e9
     total_bytes = float(mx["bytes"].sum())
+    forms = sorted({"EFIE" if a is None else f"CFIE alpha={a}" for a in info["cfie_alpha"]})
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": mx["value"],
         "unit": "matvec/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": mx["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "c64",
         "data": "synthetic",
         "config": {
-            "workload": (f"{args.workload}: " + {
-                "sphere8": "PEC sphere radius 8 lambda at 2.4 GHz, geodesic mesh nf=87 (151,380 "
-                           "triangles)",
-                "plate16": "PEC plate 16 lambda at 4.8 GHz, 144x144 squares (41,472 triangles)",
-                "plate1": "PEC plate 1 lambda at 0.3 GHz, 9x9 squares (162 triangles)",
-                "plate128": "PEC plate 128 lambda at 38.4 GHz, 1152x1152 squares",
-                "batch6": "6 scatterers in one plan at 0.3 GHz: PEC plates 2, 4, 8 lambda and spheres "
-                          "1, 2, 4 lambda (seeded vertex jitter), R right-hand sides each",
-            }[args.workload] + f"; {'EFIE' if args.cfie is None else f'CFIE (alpha {args.cfie})'}-AIM h={cfg['h_lambda']} lambda, M={cfg['order']} ({(cfg['order'] + 1) ** 3}-node "
-                               f"stencils), near radius {cfg['near_radius_lambda']} lambda; "
-                               f"N={n}, grid {info['grid'] if info['nmesh'] > 1 else info['grid'][0]}, "
-                               f"FFT {info['pad'] if info['nmesh'] > 1 else info['pad'][0]}, "
-                               f"near nnz {info['nnz_total']}; nrhs={R}"),
+            "workload": (f"{args.workload}: " + WORKLOAD_TEXT[args.workload]
+                         + f"; {' and '.join(forms)}-AIM h={cfg['h_lambda']} lambda, M={cfg['order']} "
+                         f"({(cfg['order'] + 1) ** 3}-node stencils), near radius "
+                         f"{cfg['near_radius_lambda']} lambda; N={n}, grid "
+                         f"{info['grid'] if info['nmesh'] > 1 else info['grid'][0]}, FFT "
+                         f"{info['pad'] if info['nmesh'] > 1 else info['pad'][0]}, near nnz "
+                         f"{info['nnz_total']}; nrhs={R}"),
             "systems_per_product": info["nmesh"] * R,
             "precision": "c64 grid/stencil/near arithmetic on c128 vectors (mixed path)",
+            "timing": (f"HIP events around a HIP graph of {args.steps} products, median of "
+                       f"{args.launches} launches after {args.warmup} direct products and one "
+                       f"untimed launch; per-step times from a separate pass with events "
+                       f"between the kernels"),
             "fused_projection": info["fused_projection"][0][1],
             "gather_nodes_per_wave": info["gather_npw"][0][1],
         },
@@ -524,45 +661,68 @@ def main(argv=None):
             "traffic": measured_traffic(args.workload, stage_kernel(d, fused)),
             "algorithmic_bytes_per_launch": float(mx["bytes"][d]),
             "avg_launch_ms": float(mx["stage_ms"][d]),
+            "copy_GBs": copy_gbs,
+            "frac_of_copy": achieved / copy_gbs,
         },
         "matvec_roofline": {
             "algorithmic_bytes": total_bytes,
-            "achieved_GBs": total_bytes / (mx["wall"] / args.steps) / 1e9,
-            "frac": total_bytes / (mx["wall"] / args.steps) / 1e9 / HBM_PEAK_GBS,
+            "achieved_GBs": total_bytes / (mx["ms_per_step"] * 1e-3) / 1e9,
+            "frac": total_bytes / (mx["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "frac_of_copy": total_bytes / (mx["ms_per_step"] * 1e-3) / 1e9 / copy_gbs,
         },
-        "stage_ms": {s: float(v) for s, v in zip(STAGES, mx["stage_ms"])},
-        "stage_GBs": {s: float(b / (v * 1e-3) / 1e9) for s, b, v in zip(STAGES, mx["bytes"], mx["stage_ms"])
-                      if b > 0},
+        "graph_launch_ms": [float(v) for v in mx["launch_ms"]],
+        "stage_ms": {s_: float(v) for s_, v in zip(STAGES, mx["stage_ms"])},
+        "stage_GBs": {s_: float(b / (v * 1e-3) / 1e9) for s_, b, v in zip(STAGES, mx["bytes"], mx["stage_ms"])
+                      if b > 0 and v > 0},
         "fp64": {
-            "value": R * args.steps / res["fp64"]["wall"],
-            "ms_per_step": res["fp64"]["wall"] / args.steps * 1e3,
+            "value": res["fp64"]["value"],
+            "ms_per_step": res["fp64"]["ms_per_step"],
+            "graph_launch_ms": [float(v) for v in res["fp64"]["launch_ms"]],
             "algorithmic_bytes": float(res["fp64"]["bytes"].sum()),
-            "frac": float(res["fp64"]["bytes"].sum()) / (res["fp64"]["wall"] / args.steps) / 1e9
+            "frac": float(res["fp64"]["bytes"].sum()) / (res["fp64"]["ms_per_step"] * 1e-3) / 1e9
             / HBM_PEAK_GBS,
-            "stage_ms": {s: float(v) for s, v in zip(STAGES, res["fp64"]["stage_ms"])},
+            "stage_ms": {s_: float(v) for s_, v in zip(STAGES, res["fp64"]["stage_ms"])},
         },
-        "mixed_over_fp64": res["fp64"]["wall"] / mx["wall"],
+        "mixed_over_fp64": res["fp64"]["ms_per_step"] / mx["ms_per_step"],
         "setup_s": setup_s,
         "fill": fill_report(info),
         "device_bytes": info["device_bytes"],
     }
     if args.solve_iters > 0:
-        out["solve"] = solve_compare(plan, A, mesh, args.workload, args.solve_iters)
-        if args.workload.startswith("sphere") and args.cfie is None:
-            # the paper's formulation for the closed sphere: CFIE, alpha = 0.6
-            log("[bench] CFIE (alpha 0.6) plan for the solve comparison")
-            plan_c = A.Plan([(m.verts, m.tris, m.freq_hz) for m in meshes], h_lambda=cfg["h_lambda"],
-                            order=cfg["order"], near_radius_lambda=cfg["near_radius_lambda"],
-                            cfie_alpha=0.6)
-            out["solve_cfie"] = solve_compare(plan_c, A, mesh, args.workload, args.solve_iters)
-            out["solve_cfie"]["setting"] = "CFIE alpha 0.6; " + out["solve_cfie"]["setting"]
-            plan_c.close()
+        out["solve"] = solve_compare(plan, A, mesh, args.workload, args.solve_iters, alpha)
+    plan.close()
+    if args.workload.startswith("sphere") and alpha is not None:
+        # the EFIE operator on the same sphere, for reference: product rate and
+        # the iterations its (mixed) solve needs to reach 1e-4, or the stall
+        log("[bench] EFIE plan (reference line)")
+        plan_e, _ = make_plan(None)
+        info_e = plan_e.info()
+        re_ = measure_plan(plan_e, A, info_e, R, x, y, args.steps, args.warmup, args.launches)
+        out["efie"] = {k: {"value": v["value"], "ms_per_step": v["ms_per_step"],
+                           "frac": float(v["bytes"].sum()) / (v["ms_per_step"] * 1e-3) / 1e9
+                           / HBM_PEAK_GBS} for k, v in re_.items()}
+        if args.solve_iters > 0:
+            import torch as _t
+
+            plan_e.solve([(0.0, 0.0, 0)], A.AIM_MIXED, tol=1e-4, max_iter=2, raise_on_noconv=False)
+            _t.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = plan_e.solve([(0.0, 0.0, 0)], A.AIM_MIXED, tol=1e-4, restart=100,
+                                 max_iter=args.solve_iters, raise_on_noconv=False)
+            _t.cuda.synchronize()
+            out["efie"]["solve_mixed"] = dict(iterations=st[0]["iterations"],
+                                              converged=st[0]["converged"],
+                                              residual=st[0]["residual"],
+                                              seconds=time.perf_counter() - t0,
+                                              cap=args.solve_iters)
+            log(f"[bench] EFIE solve: {st[0]['iterations']} its, residual {st[0]['residual']:.3e}")
+        plan_e.close()
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(mesh, cfg, R, tuple(info["pad"][0]), args.cfie)
+        out["cpu_baseline"] = cpu_baseline(mesh, cfg, R, tuple(info["pad"][0]),
+                                           info["cfie_alpha"][0])
         out["fill"]["cpu_oracle"] = cpu_fill_baseline(cfg, mesh.freq_hz)
     print(json.dumps(out), flush=True)
-    plan.close()
 
 
 if __name__ == "__main__":
