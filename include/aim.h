@@ -304,6 +304,23 @@ aim_status aim_rcs(aim_plan *plan, int32_t nrhs, const void *x, int32_t ntheta,
                    const double *theta, int32_t nphi, const double *phi,
                    double *sigma_tt, void *hip_stream);
 
+/* aim_rcs without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid it): the same sigma_theta_theta, with theta, phi and sigma_tt in
+ * device memory (theta[ntheta], phi[nphi] radians; sigma_tt [nmesh][nrhs]
+ * [ntheta][nphi], m^2) and x as for aim_rcs; asynchronous on hip_stream, on
+ * the plan's device (else AIM_ERR_ARG). Each quadrature point's current is
+ * formed inside the kernel, and the partial sums over point chunks live in a
+ * fixed array of 1,048,576 complex doubles (16 MiB) that the library holds on
+ * each GPU it runs on until the process ends: ntheta * nphi * nrhs above
+ * that gives AIM_ERR_ARG. Every call on a GPU shares that GPU's array (each
+ * call writes every partial it reads, so nothing needs clearing), so calls
+ * that overlap in time on one GPU, on different streams or threads, race;
+ * calls ordered on one stream do not. */
+aim_status aim_rcs_noalloc(aim_plan *plan, int32_t nrhs, const void *x, int32_t ntheta,
+                           const double *theta, int32_t nphi, const double *phi,
+                           double *sigma_tt, void *hip_stream);
+
 /* ---- host-only planning (no GPU needed) -------------------------------- */
 
 /* Runs only the host phase of aim_setup for one mesh: validation, RWG table,

@@ -39,13 +39,14 @@ AIM_DATA_ZDIAG64 = 3
 AIM_DATA_GHAT64 = 4
 AIM_DATA_CURL64 = 5
 AIM_NSETUP = 5
+AIM_RCS_SCRATCH_ELEMS = 1 << 20  # partial sums held by aim_rcs_noalloc's fixed array
 # set-up phases of aim_info.setup_ms, in order
 SETUP_PHASES = ("host_plan", "projection", "green", "near_fill", "tune")
 
 EXPORTED = [
     "aim_setup", "aim_plan_info", "aim_destroy", "aim_matvec", "aim_matvec_timed",
     "aim_matvec_graph_timed", "aim_gmres_solve",
-    "aim_excitation", "aim_rcs", "aim_host_plan_build", "aim_host_plan_export",
+    "aim_excitation", "aim_rcs", "aim_rcs_noalloc", "aim_host_plan_build", "aim_host_plan_export",
     "aim_host_plan_destroy", "aim_export", "aim_debug_far_stage", "aim_debug_product_stage",
     "aim_last_error",
 ]
@@ -129,6 +130,7 @@ def lib():
         "aim_excitation": [P, c_int32, POINTER(AimPlanewave), P, P],
         "aim_rcs": [P, c_int32, P, c_int32, POINTER(c_double), c_int32, POINTER(c_double),
                     POINTER(c_double), P],
+        "aim_rcs_noalloc": [P, c_int32, P, c_int32, P, c_int32, P, P, P],
         "aim_host_plan_build": [POINTER(AimMesh), POINTER(AimParams), POINTER(P)],
         "aim_host_plan_export": [P, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32),
                                  POINTER(c_int32), POINTER(c_int64), POINTER(c_int32),
@@ -414,6 +416,28 @@ class Plan:
                              th.ctypes.data_as(POINTER(c_double)), ph.size,
                              ph.ctypes.data_as(POINTER(c_double)),
                              out.ctypes.data_as(POINTER(c_double)), self._stream(stream)))
+        return out
+
+    def rcs_noalloc(self, x, theta, phi, out=None, stream=None):
+        """aim_rcs_noalloc: sigma_tt (nmesh, nrhs, ntheta, nphi) on the device
+        for currents x (nrhs, n_total) complex128 and directions theta, phi
+        (float64 device tensors); asynchronous. `out` (float64 device tensor
+        of that shape) receives it if given."""
+        torch = self._torch
+        nrhs = check_vectors(x, None, self.n_total, torch.complex128, self.device)
+        for name, t in (("theta", theta), ("phi", phi)):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.dim() != 1:
+                raise ValueError(f"{name} must be a contiguous 1-D float64 device tensor")
+        shape = (self.nmesh, nrhs, theta.numel(), phi.numel())
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float64, device=x.device)
+        elif (out.dtype != torch.float64 or tuple(out.shape) != shape or not out.is_cuda
+              or not out.is_contiguous()):
+            raise ValueError(f"out must be a contiguous float64 device tensor of shape {shape}")
+        _check(lib().aim_rcs_noalloc(self._h, nrhs, c_void_p(x.data_ptr()), theta.numel(),
+                                     c_void_p(theta.data_ptr()), phi.numel(),
+                                     c_void_p(phi.data_ptr()), c_void_p(out.data_ptr()),
+                                     self._stream(stream)))
         return out
 
     def export(self, mesh: int, what: int):

@@ -182,6 +182,9 @@ struct MeshDev {
   // grids with them)
   double *curl64 = nullptr;  // n*3*K
   float *curl32 = nullptr;
+  // per triangle and local vertex i: (basis << 1 | side) of the basis whose
+  // free vertex is vertex i (side 1 on T-), or -1 (far field, RCS)
+  int32_t *tri_basis = nullptr;  // nt*3
   // projected source grids per precision [4 nrhs][V0] (the plane's [4 nrhs]
   // [Nx Ny] for a planar scatterer): zero once when allocated, after which the
   // projection writes the occupied nodes only (the same nodes every product)
@@ -208,6 +211,7 @@ void *dev_alloc(Plan *pl, size_t bytes);
 void dev_free(Plan *pl, void *p);
 
 struct Plan {
+  int device = 0;  // HIP device the plan was set up on
   aim_allocator alloc{};
   bool own_alloc = true;
   hipStream_t setup_stream = nullptr;
@@ -303,6 +307,19 @@ void excitation_mesh(Plan *pl, MeshDev &md, int nw, const aim_planewave *w, doub
                      hipStream_t s);
 void rcs_mesh(Plan *pl, MeshDev &md, int nrhs, const double2 *x, int64_t ldx, int ntheta,
               const double *theta, int nphi, const double *phi, double *sigma, hipStream_t s);
+// the triangle -> basis table of the far field (set-up)
+void rcs_prepare_mesh(Plan *pl, MeshDev &md, hipStream_t s);
+// address of the current device's fixed RCS scratch array, looked up once per
+// device (set-up)
+void rcs_scratch_init();
+// elements (double2) of that array, and the current device's address of it
+constexpr int64_t kRcsScratchElems = int64_t(1) << 20;
+void *rcs_scratch_ptr(int device);
+// the RCS without allocation: device directions and output, partial sums in
+// the fixed scratch array (asynchronous)
+void rcs_mesh_noalloc(MeshDev &md, int nrhs, const double2 *x, int64_t ldx, int ntheta,
+                      const double *theta, int nphi, const double *phi, double *sigma,
+                      double2 *part, hipStream_t s);
 
 // solver (solver.hip)
 aim_status gmres_solve(Plan *pl, aim_precision prec, int nrhs, const aim_planewave *waves,

@@ -184,6 +184,8 @@ aim_status aim_setup(const aim_mesh *meshes, int32_t nmesh, const aim_params *p,
   pl->nmesh = nmesh;
   pl->mesh.resize(nmesh);
   aim_status st = guarded([&] {
+    HIPCHECK(hipGetDevice(&pl->device));
+    rcs_scratch_init();  // the device address of the allocation-free RCS's fixed array
     int64_t off = 0;
     for (int i = 0; i < nmesh; ++i) {
       const double t0 = wall_ms();
@@ -424,6 +426,27 @@ aim_status aim_rcs(aim_plan *plan, int32_t nrhs, const void *x, int32_t ntheta, 
       MeshDev &md = plan->mesh[i];
       rcs_mesh(plan, md, nrhs, (const double2 *)x + md.offset, plan->n_total, ntheta, theta, nphi,
                phi, sigma_tt + i * per, (hipStream_t)hip_stream);
+    }
+  });
+}
+
+aim_status aim_rcs_noalloc(aim_plan *plan, int32_t nrhs, const void *x, int32_t ntheta,
+                           const double *theta, int32_t nphi, const double *phi, double *sigma_tt,
+                           void *hip_stream) {
+  if (!plan || !x || !theta || !phi || !sigma_tt || nrhs < 1 || ntheta < 1 || nphi < 1)
+    return fail(AIM_ERR_ARG, "bad argument");
+  return guarded([&] {
+    int dev = -1;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev != plan->device)
+      throw Error(AIM_ERR_ARG, "aim_rcs_noalloc: the plan's device is not the current device");
+    double2 *part = (double2 *)rcs_scratch_ptr(plan->device);
+    if (!part) throw Error(AIM_ERR_STATE, "aim_rcs_noalloc: scratch address not initialised");
+    const int64_t per = (int64_t)nrhs * ntheta * nphi;
+    for (int i = 0; i < plan->nmesh; ++i) {
+      MeshDev &md = plan->mesh[i];
+      rcs_mesh_noalloc(md, nrhs, (const double2 *)x + md.offset, plan->n_total, ntheta, theta,
+                       nphi, phi, sigma_tt + i * per, part, (hipStream_t)hip_stream);
     }
   });
 }

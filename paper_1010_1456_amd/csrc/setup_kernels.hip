@@ -719,6 +719,7 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
   dev_free(pl, gtab);
   dev_free(pl, anchor3);
   md.area = area;  // kept for excitation and RCS
+  rcs_prepare_mesh(pl, md, s);
 }
 
 void excitation_mesh(Plan *pl, MeshDev &md, int nw, const aim_planewave *w, double2 *b,
