@@ -182,6 +182,17 @@ def stage_bytes(info, mesh, nrhs, s_grid, s_real, s_x, s_y, path):
     ], dtype=np.float64)
 
 
+def pipelined_bytes(info, mesh, path, b):
+    """With the y, x and y passes pipelined in one kernel (aim_info.xy_groups
+    > 1) their stage boundaries fall together and the forward y step carries
+    the time of all three: so does its byte count."""
+    if info["xy_groups"][mesh][path] > 1:
+        b = b.copy()
+        b[2] += b[3] + b[4]
+        b[3] = b[4] = 0.0
+    return b
+
+
 def fill_report(info):
     """Set-up (matrix fill) phase times of the plan, summed over scatterers,
     and the near-zone fill rate: FP64 entries of Z^MOM - Z^grid per second."""
@@ -519,7 +530,8 @@ def measure_plan(plan, A, info, R, x, y, steps, warmup, launches):
                                      ("fp64", A.AIM_FP64, 16, 8, 0)):
         log(f"[bench] timing {name}: {warmup} warm-up, {launches} graph launches of {steps} products")
         launch_ms, st_ms, wall = time_path(plan, A, prec, x, y, steps, warmup, launches)
-        b = sum(stage_bytes(info, mi, R, sg, sr, 16, 16, path) for mi in range(info["nmesh"]))
+        b = sum(pipelined_bytes(info, mi, path, stage_bytes(info, mi, R, sg, sr, 16, 16, path))
+                for mi in range(info["nmesh"]))
         med = float(np.median(launch_ms))
         res[name] = dict(launch_ms=launch_ms, ms_per_step=med / steps, stage_ms=st_ms, bytes=b,
                          wall=wall, value=R * steps / (med * 1e-3))
@@ -548,6 +560,8 @@ def main(argv=None):
                          "open ones keep the EFIE")
     ap.add_argument("--efie", action="store_true",
                     help="the EFIE on every scatterer (closed ones too)")
+    ap.add_argument("--xy-groups", type=int, default=0, choices=[0, 1, 2, 4],
+                    help="field groups of the pipelined y / x / y passes (0: chosen at set-up)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--solve-iters", type=int, default=3000,
                     help="GMRES iteration cap of the solve comparison (0 skips it)")
@@ -601,7 +615,7 @@ def main(argv=None):
         t0 = time.perf_counter()
         pl = A.Plan([(m.verts, m.tris, m.freq_hz) for m in meshes], h_lambda=cfg["h_lambda"],
                     order=cfg["order"], near_radius_lambda=cfg["near_radius_lambda"],
-                    cfie_alpha=a, cfie_closed_only=True)
+                    cfie_alpha=a, cfie_closed_only=True, xy_groups=args.xy_groups)
         torch.cuda.synchronize()
         return pl, time.perf_counter() - t0
 
@@ -609,7 +623,7 @@ def main(argv=None):
     info = plan.info()
     n = info["n_total"]
     log(f"[bench] set-up {setup_s:.2f} s: N={n} grid={info['grid'][0]} pad={info['pad'][0]} "
-        f"nnz={info['nnz_total']} cfie={info['cfie_alpha']}")
+        f"nnz={info['nnz_total']} cfie={info['cfie_alpha']} xy_groups={info['xy_groups']}")
     R = args.nrhs if args.nrhs is not None else (16 if args.workload == "batch6" else 1)
     x = torch.from_numpy(random_current(n, nrhs=R, seed=7)).cuda()
     y = torch.empty_like(x)
@@ -617,7 +631,11 @@ def main(argv=None):
 
     mx = res["mixed"]
     fused = bool(info["fused_projection"][0][1])  # (first scatterer's variant names the kernel)
+    piped = info["xy_groups"][0][1] > 1
     d = int(np.argmax(mx["stage_ms"]))
+    kname = ("k_fft_xy<float> (fwd_y + x_green + inv_y pipelined over "
+             f"{info['xy_groups'][0][1]} field groups)" if piped and d == 2
+             else stage_kernel(d, fused) + f"> ({STAGES[d]})")
     achieved = mx["bytes"][d] / (mx["stage_ms"][d] * 1e-3) / 1e9
     total_bytes = float(mx["bytes"].sum())
     forms = sorted({"EFIE" if a is None else f"CFIE alpha={a}" for a in info["cfie_alpha"]})
@@ -650,15 +668,17 @@ def main(argv=None):
                        f"between the kernels"),
             "fused_projection": info["fused_projection"][0][1],
             "gather_nodes_per_wave": info["gather_npw"][0][1],
+            "xy_pipeline_groups": info["xy_groups"][0][1],
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": stage_kernel(d, fused) + f"> ({STAGES[d]})",
+            "kernel": kname,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.workload, stage_kernel(d, fused)),
+            "traffic": measured_traffic(args.workload, "k_fft_xy<float" if piped and d == 2
+                                        else stage_kernel(d, fused)),
             "algorithmic_bytes_per_launch": float(mx["bytes"][d]),
             "avg_launch_ms": float(mx["stage_ms"][d]),
             "copy_GBs": copy_gbs,

@@ -83,6 +83,11 @@ typedef struct {
  * fft_min_pad         0: FFT length per dimension = smallest supported
  *                     length >= 2 N_d - 1; otherwise a lower bound on it
  * flags               AIM_FLAG_* below
+ * xy_groups           0: the set-up picks by timing how many field groups the
+ *                     forward y, x and inverse y passes are pipelined over
+ *                     (aim_info.xy_groups); 1, 2 or 4: that many wherever the
+ *                     pipeline applies (for tests and measurements); other
+ *                     values give AIM_ERR_ARG
  * cfie_alpha          with AIM_FLAG_CFIE: the combination parameter alpha in
  *                     [0, 1] of alpha EFIE + (1 - alpha) eta MFIE (the paper
  *                     uses 0.6 for its closed scatterers, Section 2.2);
@@ -93,7 +98,7 @@ typedef struct {
   int32_t fft_min_pad;
   double near_radius_lambda;
   int32_t flags;
-  int32_t reserved;
+  int32_t xy_groups;
   double cfie_alpha;
 } aim_params;
 
@@ -185,6 +190,11 @@ typedef struct {
                                            the z passes transform) */
   int32_t gather_npw[AIM_MAX_MESH][2];  /* [mesh][0 FP64, 1 mixed]: occupied nodes per wave of
                                            the projection gather (chosen by timing at set-up) */
+  int32_t xy_groups[AIM_MAX_MESH][2];   /* [mesh][0 FP64, 1 mixed]: field groups over which the
+                                           forward y, x and inverse y passes run pipelined, the
+                                           x pass of one group beside the y passes of others in
+                                           one launch (1: one pass after the other; chosen by
+                                           timing at set-up) */
 } aim_info;
 
 /* GMRES options. restart m (<= 200), relative-residual tolerance on

@@ -24,7 +24,8 @@ ARCH = "gfx950"
 
 SOURCES = ["host_plan.cpp", "api.hip", "setup_kernels.hip", "matvec.hip", "solver.hip", "rcs.hip",
            "fft_contig_f32.hip", "fft_contig_f64.hip", "fft_strided_f32.hip", "fft_strided_f64.hip",
-           "fft_mid_f32.hip", "fft_mid_f64.hip", "fft_anterp_f32.hip", "fft_anterp_f64.hip"]
+           "fft_mid_f32.hip", "fft_mid_f64.hip", "fft_anterp_f32.hip", "fft_anterp_f64.hip",
+           "fft_xy_f32.hip", "fft_xy_f64.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
           "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-but-set-variable",

@@ -176,6 +176,9 @@ struct MeshDev {
   // occupied nodes per wave of the projection gather, per precision [FP64,
   // FP32]: chosen by timing at set-up among 8, 16, 32
   int gather_npw[2] = {16, 16};
+  // field groups of the pipelined y / x / y passes per precision (1: the
+  // three passes one after the other), chosen by timing at set-up
+  int xy_groups[2] = {1, 1};
   double setup_ms[AIM_NSETUP] = {0, 0, 0, 0, 0};  // wall time per set-up phase
   // combined field only: curl weights W[n][e][u] = int (t_n x grad l_u)_e,
   // t_n = f_n x n (the MFIE part is interpolated from the vector potential's
@@ -256,6 +259,19 @@ struct ContigMap;
 AIM_DECLARE_FFT(float2)
 AIM_DECLARE_FFT(double2)
 #undef AIM_DECLARE_FFT
+
+// the y, x and y passes of the kz-blocked layout pipelined over G field
+// groups in G + 2 launches (fft_xy_*.hip); false if the lengths have no
+// pipelined kernel (then nothing is launched)
+bool xy_pipeline_available(const FftPlan &plx, const FftPlan &ply);
+#define AIM_DECLARE_XY(V)                                                                         \
+  void fft_xy_pipeline(const V *gz, V *g2, V *g1, const FftPlan &pl, int Nx, int Ny, int F,       \
+                       int G, int Py, int Pz, int Hy, int Hz, const V *ghat, const V *twx,        \
+                       const V *twy, int blk, int64_t V2, const fftk::LineMap &m1y,               \
+                       const fftk::LineMap &m2, hipStream_t s);
+AIM_DECLARE_XY(float2)
+AIM_DECLARE_XY(double2)
+#undef AIM_DECLARE_XY
 
 // anterpolation fused with the forward z pass (fft_anterp_*.hip): x (c64 or
 // c128) -> forward z transforms of the 4 source fields, [4 nrhs][nlines][out_ls]

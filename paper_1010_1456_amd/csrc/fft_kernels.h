@@ -182,18 +182,20 @@ __global__ void __launch_bounds__((threads_contig<T, PC>()))
   });
 }
 
+// One work-group of a strided pass: tile vb = o ntile + (c0 / B) covers the
+// B lines (o, c0 .. c0 + B - 1).
 template <typename T, bool INV, bool PR, class PC>
-__global__ void __launch_bounds__((threads_strided<T, PC>()))
-    k_fft_strided(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, int n_in, int n_out,
-                  int64_t inner, int ntile, LineMap imap, LineMap omap,
-                  const cx<T> *__restrict__ tw, int) {
+__device__ __forceinline__ void strided_body(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
+                                             int n_in, int n_out, int64_t inner, int ntile,
+                                             const LineMap &imap, const LineMap &omap,
+                                             const cx<T> *__restrict__ tw, int64_t vb) {
   using V = cx<T>;
   extern __shared__ unsigned char smem_raw[];
   V *lds = reinterpret_cast<V *>(smem_raw);
   constexpr int P = PC::P;
   constexpr int B = tile_strided<T, PC>();
-  const int64_t o = blockIdx.x / ntile;
-  const int64_t c0 = (int64_t)(blockIdx.x % ntile) * B;
+  const int64_t o = vb / ntile;
+  const int64_t c0 = (vb % ntile) * B;
   const int b = threadIdx.x % B;
   const int beta = threadIdx.x / B;
   const bool line_ok = (c0 + b < inner);
@@ -250,6 +252,14 @@ __global__ void __launch_bounds__((threads_strided<T, PC>()))
     if (active) stage_compute_store_p<R, INV, uz, nout, false>(v, beta, L, Mp, twl, st);
     if constexpr (!last) __syncthreads();
   });
+}
+
+template <typename T, bool INV, bool PR, class PC>
+__global__ void __launch_bounds__((threads_strided<T, PC>()))
+    k_fft_strided(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, int n_in, int n_out,
+                  int64_t inner, int ntile, LineMap imap, LineMap omap,
+                  const cx<T> *__restrict__ tw, int) {
+  strided_body<T, INV, PR, PC>(in, out, n_in, n_out, inner, ntile, imap, omap, tw, blockIdx.x);
 }
 
 // x pass: forward transform along x, spectrum multiply and inverse transform
@@ -313,11 +323,13 @@ struct MidLds {
   static constexpr int total = data + flat + mid_rows + last_rows;
 };
 
+// One work-group of the x pass: vb is the launch's block number (XCD vb % 8).
 template <typename T, class PC, bool KYL>
-__global__ void __launch_bounds__((threads_mid<T, PC>()), (mid_min_waves<T>()))
-    k_fft_mid(cx<T> *__restrict__ data, int n_x, int nfield, int Py, int Pz, int ntile, int slots,
-              int Hy, int Hz, const cx<T> *__restrict__ ghat, const cx<T> *__restrict__ tw, int blk,
-              int64_t fstride) {
+__device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int nfield, int Py,
+                                         int Pz, int ntile, int slots, int Hy, int Hz,
+                                         const cx<T> *__restrict__ ghat,
+                                         const cx<T> *__restrict__ tw, int blk, int64_t fstride,
+                                         int64_t vb) {
   using V = cx<T>;
   using ML = MidLds<T, PC>;
   extern __shared__ unsigned char smem_raw[];
@@ -341,7 +353,7 @@ __global__ void __launch_bounds__((threads_mid<T, PC>()), (mid_min_waves<T>()))
   // t = nfield (2 (ff ntile + kt) + m) + field: fixed index ff (m = 0) or its
   // mirror Pf - ff (m = 1), which reads the same octant rows, tile kt.
   const int Pt = KYL ? Py : Pz, Pf = KYL ? Pz : Py;
-  const int t = (int)(blockIdx.x % kXcd) * slots + (int)(blockIdx.x / kXcd);
+  const int t = (int)(vb % kXcd) * slots + (int)(vb / kXcd);
   const int field = t % nfield, tt = t / nfield;
   const int m = tt & 1, rest = tt >> 1;
   const int ff = rest / ntile;
@@ -523,6 +535,71 @@ __global__ void __launch_bounds__((threads_mid<T, PC>()), (mid_min_waves<T>()))
   }
 }
 
+template <typename T, class PC, bool KYL>
+__global__ void __launch_bounds__((threads_mid<T, PC>()), (mid_min_waves<T>()))
+    k_fft_mid(cx<T> *__restrict__ data, int n_x, int nfield, int Py, int Pz, int ntile, int slots,
+              int Hy, int Hz, const cx<T> *__restrict__ ghat, const cx<T> *__restrict__ tw, int blk,
+              int64_t fstride) {
+  mid_body<T, PC, KYL>(data, n_x, nfield, Py, Pz, ntile, slots, Hy, Hz, ghat, tw, blk, fstride,
+                       blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// The y passes and the x pass of a field group in one launch (kz-blocked
+// layout, P_x = P_y). The x pass is bound by vector-ALU issue (two FFTs per
+// element loaded), the y passes by HBM traffic, so running them side by side
+// keeps both busy: the fields are split into G groups and launch t runs the
+// x pass of group t - 1 together with the forward y pass of group t and the
+// inverse y pass of group t - 2 (G + 2 launches in all). The launch's blocks
+// come in runs of 8 (one per XCD); each run has one role, and the roles are
+// spread evenly over the launch so every CU mixes them.
+template <typename T>
+struct XyStrided {
+  const cx<T> *in;
+  cx<T> *out;
+  int n_in, n_out;
+  int64_t inner;
+  int ntile;
+  LineMap imap, omap;
+  int64_t b0, nb;  // first tile of this launch's lines, tiles in it
+};
+template <typename T>
+struct XyMid {
+  cx<T> *data;  // first field of the group
+  int n_x, nfield, Py, Pz, ntile, slots, Hy, Hz, blk;
+  int64_t fstride;
+  int64_t nb;  // blocks of the x pass (slots * 8), 0: none in this launch
+};
+
+template <typename T, class PC>
+constexpr int threads_xy() {
+  return threads_mid<T, PC>() > threads_strided<T, PC>() ? threads_mid<T, PC>()
+                                                         : threads_strided<T, PC>();
+}
+
+template <typename T, class PC, bool PRF, bool PRI>
+__global__ void __launch_bounds__((threads_xy<T, PC>()), (mid_min_waves<T>()))
+    k_fft_xy(XyMid<T> xm, XyStrided<T> yf, XyStrided<T> yi, const cx<T> *__restrict__ ghat,
+             const cx<T> *__restrict__ twx, const cx<T> *__restrict__ twy, int64_t nruns,
+             int64_t yruns) {
+  const int64_t run = blockIdx.x / kXcd, xcd = blockIdx.x % kXcd;
+  const int64_t ylo = run * yruns / nruns, yhi = (run + 1) * yruns / nruns;
+  if (yhi > ylo) {  // a y run: forward tiles first, then inverse ones
+    const int64_t v = ylo * kXcd + xcd;
+    if (v < yf.nb)
+      strided_body<T, false, PRF, PC>(yf.in, yf.out, yf.n_in, yf.n_out, yf.inner, yf.ntile,
+                                      yf.imap, yf.omap, twy, yf.b0 + v);
+    else if (v - yf.nb < yi.nb)
+      strided_body<T, true, PRI, PC>(yi.in, yi.out, yi.n_in, yi.n_out, yi.inner, yi.ntile,
+                                     yi.imap, yi.omap, twy, yi.b0 + (v - yf.nb));
+    return;
+  }
+  const int64_t v = (run - ylo) * kXcd + xcd;  // x runs keep the XCD of their block
+  if (v < xm.nb)
+    mid_body<T, PC, false>(xm.data, xm.n_x, xm.nfield, xm.Py, xm.Pz, xm.ntile, xm.slots, xm.Hy,
+                           xm.Hz, ghat, twx, xm.blk, xm.fstride, v);
+}
+
 template <typename T, class PC>
 void launch_contig(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t lines,
                    const ContigMap &imap, const ContigMap &omap, bool inverse, const cx<T> *tw,
@@ -598,6 +675,63 @@ void launch_mid(cx<T> *data, int n_x, int nfield, int Py, int Pz, int Hy, int Hz
                        lds, s, data, n_x, nfield, Py, Pz, ntile, (int)slots, Hy, Hz, ghat, tw, blk,
                        fstride);
   LAUNCHCHECK();
+}
+
+// The pipelined y, x and y passes of the kz-blocked layout (see k_fft_xy):
+// forward y pass gz -> g2 (line maps m1y -> m2), x pass with the spectrum on
+// g2 in place, inverse y pass g2 -> g1 (m2 -> m1y), over F fields in G groups.
+template <typename T, class PC>
+void launch_xy(const cx<T> *gz, cx<T> *g2, cx<T> *g1, int Nx, int Ny, int F, int G, int Py,
+               int Pz, int Hy, int Hz, const cx<T> *ghat, const cx<T> *twx, const cx<T> *twy,
+               int blk, int64_t V2, const LineMap &m1y, const LineMap &m2, hipStream_t s) {
+  constexpr int B = tile_mid<T, PC>();
+  static_assert(tile_strided<T, PC>() == B, "x and y tiles differ");
+  constexpr int threads = threads_xy<T, PC>();
+  constexpr bool PRF = PC::r(0) % 2 == 0, PRI = PC::r(PC::ns - 1) % 2 == 0;
+  if (G < 1 || F % G != 0) throw Error(AIM_ERR_ARG, "y/x pipeline: groups do not divide the fields");
+  if (Py != PC::P) throw Error(AIM_ERR_ARG, "y/x pipeline: x and y lengths differ");
+  // pruned first / last stages: at most P/2 sources per x and y line
+  if ((PRF || PRI) && (2 * Nx > PC::P || 2 * Ny > PC::P))
+    throw Error(AIM_ERR_ARG, "y/x pipeline: more than P/2 sources on a line");
+  if (blk <= 0 || blk % B != 0) throw Error(AIM_ERR_ARG, "y/x pipeline: tile does not divide the kz block");
+  if ((uint64_t)Nx * Py * blk * sizeof(cx<T>) >= (1ull << 31) ||
+      (uint64_t)Hy * Hz * (PC::P / 2 + 1) * sizeof(cx<T>) >= (1ull << 31))
+    throw Error(AIM_ERR_ARG, "y/x pipeline: grid too large for 32-bit offsets");
+  const int Fg = F / G;
+  const int ntile = (Pz + B - 1) / B;  // kz tiles (both passes)
+  const int64_t ynb = (int64_t)Fg * Nx * ntile;
+  const int64_t items = 2 * ((int64_t)Py / 2 + 1) * ntile * Fg;
+  const int64_t slots = (items + kXcd - 1) / kXcd;
+  if (slots * kXcd > INT32_MAX) throw Error(AIM_ERR_ARG, "y/x pipeline: too many tiles");
+  const size_t lds = (size_t)std::max(MidLds<T, PC>::total, PC::P * (B + 1)) * sizeof(cx<T>);
+  for (int t = 0; t <= G + 1; ++t) {
+    XyMid<T> xm{};
+    if (t >= 1 && t <= G) {
+      xm.data = g2 + (int64_t)(t - 1) * Fg * V2;
+      xm.n_x = Nx;
+      xm.nfield = Fg;
+      xm.Py = Py;
+      xm.Pz = Pz;
+      xm.ntile = ntile;
+      xm.slots = (int)slots;
+      xm.Hy = Hy;
+      xm.Hz = Hz;
+      xm.blk = blk;
+      xm.fstride = V2;
+      xm.nb = slots * kXcd;
+    }
+    XyStrided<T> yf{gz, g2, Ny, Py, Pz, ntile, m1y, m2, (int64_t)t * ynb, t < G ? ynb : 0};
+    XyStrided<T> yi{g2, g1, Py, Ny, Pz, ntile, m2, m1y, (int64_t)(t - 2) * ynb,
+                    (t >= 2 && t - 2 < G) ? ynb : 0};
+    const int64_t xruns = xm.nb / kXcd;
+    const int64_t yruns = (yf.nb + yi.nb + kXcd - 1) / kXcd;
+    const int64_t nruns = xruns + yruns;
+    if (nruns == 0) continue;
+    if (nruns * kXcd > INT32_MAX) throw Error(AIM_ERR_ARG, "y/x pipeline: launch too large");
+    hipLaunchKernelGGL((k_fft_xy<T, PC, PRF, PRI>), dim3((unsigned)(nruns * kXcd)), dim3(threads),
+                       lds, s, xm, yf, yi, ghat, twx, twy, nruns, yruns);
+    LAUNCHCHECK();
+  }
 }
 
 [[noreturn]] inline void bad_length(int P) {

@@ -589,17 +589,31 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     v.blk = blk;
     v.fstride = V2;
   };
-  fft_pass_strided(gz, g2, md.plan[1], Ny, Py, F * Nx, Pz, m1y, m2, false, tw_of<T>(md, 1), s);
-  mark(3);
-  blocked_view(3);
-  if (stop <= 3) return;
-  fft_mid_pass(g2, md.plan[0], Nx, (int)F, Py, Pz, md.H[0], md.H[1], md.H[2], ghat_of<T>(md),
-               tw_of<T>(md, 0), blk, V2, s);
-  mark(4);
-  blocked_view(4);
-  if (stop <= 4) return;
-  fft_pass_strided(g2, g1, md.plan[1], Py, Ny, F * Nx, Pz, m2, m1y, true, tw_of<T>(md, 1), s);
-  mark(5);
+  // the y, x and y passes pipelined over field groups (tuned at set-up) when
+  // the product runs through; the stage boundaries then fall together (the
+  // forward y step carries the time of all three)
+  const int G = md.xy_groups[prec];
+  if (stop >= 6 && !full3d && G > 1 && F % G == 0 &&
+      xy_pipeline_available(md.plan[0], md.plan[1])) {
+    fft_xy_pipeline(gz, g2, g1, md.plan[0], Nx, Ny, (int)F, G, Py, Pz, md.H[1], md.H[2],
+                    ghat_of<T>(md), tw_of<T>(md, 0), tw_of<T>(md, 1), blk, V2, m1y, m2, s);
+    mark(3);
+    mark(4);
+    blocked_view(4);
+    mark(5);
+  } else {
+    fft_pass_strided(gz, g2, md.plan[1], Ny, Py, F * Nx, Pz, m1y, m2, false, tw_of<T>(md, 1), s);
+    mark(3);
+    blocked_view(3);
+    if (stop <= 3) return;
+    fft_mid_pass(g2, md.plan[0], Nx, (int)F, Py, Pz, md.H[0], md.H[1], md.H[2], ghat_of<T>(md),
+                 tw_of<T>(md, 0), blk, V2, s);
+    mark(4);
+    blocked_view(4);
+    if (stop <= 4) return;
+    fft_pass_strided(g2, g1, md.plan[1], Py, Ny, F * Nx, Pz, m2, m1y, true, tw_of<T>(md, 1), s);
+    mark(5);
+  }
   view(5, g1, (int64_t)Nx * Ny, Pz, (int64_t)Nx * Ny * Pzs, Pzs, 1);
   if (stop <= 5) return;
   if (full3d) {  // inspection: every line
@@ -784,6 +798,30 @@ void autotune_mesh(Plan *pl, MeshDev &md, hipStream_t s) {
         }
       }
       md.fuse_proj[prec] = choice;
+    }
+    // field groups of the pipelined y / x / y passes (kz-blocked grids with
+    // equal x and y lengths)
+    for (int prec = 0; prec < 2; ++prec) {
+      if (prec == 1 && !pl->mixed) break;
+      md.xy_groups[prec] = 1;
+      const bool thin = prec == 0 ? thin_layout<double>(md.hp.pad[2]) : thin_layout<float>(md.hp.pad[2]);
+      if (thin || md.planar_z >= 0 || !xy_pipeline_available(md.plan[0], md.plan[1])) continue;
+      const int forced = pl->params.xy_groups;
+      if (forced > 0) {
+        md.xy_groups[prec] = forced;
+        continue;
+      }
+      float best = 0;
+      int choice = 1;
+      for (int g : {1, 2, 4}) {
+        md.xy_groups[prec] = g;
+        const float ms = time_stages(prec, 6);
+        if (g == 1 || ms < best) {
+          best = ms;
+          choice = g;
+        }
+      }
+      md.xy_groups[prec] = choice;
     }
   } catch (...) {
     (void)hipEventDestroy(e0);

@@ -448,3 +448,85 @@ def test_product_after_inspection_on_an_l_shaped_plate():
         assert rel_max(y[r], ref[r]) <= 1e-10
         assert rel(y32[r], ref[r]) <= 1e-4
     plan.close()
+
+
+# Spheres whose FFT lengths have pipelined y / x / y kernels: 72 = 9 x 8 (odd
+# first radix, even last), 81 = 9 x 9 (no pruned stage), 144 = 12 x 12 (both
+# pruned), meshed coarsely so that the oracle's operator builds in seconds.
+PIPE_CASES = {
+    "sphere165": (lambda: sphere_mesh(1.65, 0.3e9, nf=10), 72),
+    "sphere2": (lambda: sphere_mesh(2.0, 0.3e9, nf=8), 81),
+    "sphere355": (lambda: sphere_mesh(3.55, 0.3e9, nf=14), 144),
+}
+_pipe_ops = {}
+
+
+def _pipe_case(name):
+    if name not in _pipe_ops:
+        m = PIPE_CASES[name][0]()
+        k = wavenumber(m.freq_hz)
+        rwg = build_rwg(m.verts, m.tris)
+        _log(f"[pipeline {name}] oracle set-up N={rwg.n}")
+        op = oaim.build_operator(rwg, k, 0.1 * m.lam, 2, 0.3 * m.lam)
+        _pipe_ops[name] = (m, rwg, op)
+    return _pipe_ops[name]
+
+
+@pytest.mark.parametrize("name", list(PIPE_CASES))
+@pytest.mark.parametrize("groups", [2, 4])
+def test_pipelined_passes(name, groups):
+    """The forward y, x and inverse y passes pipelined over field groups (one
+    launch holding the x pass of one group beside the y passes of others):
+    products with 1 and 3 right-hand sides against the oracle, both paths,
+    and the grids the pipeline leaves (x pass, inverse y pass) against numpy
+    FFTs of the oracle's projected grids."""
+    from paper_1010_1456_amd import aim as A
+
+    m, rwg, op = _pipe_case(name)
+    plan = A.Plan([(m.verts, m.tris, m.freq_hz)], xy_groups=groups)
+    inf = plan.info()
+    assert inf["pad"][0][0] == PIPE_CASES[name][1] == inf["pad"][0][1]
+    assert inf["xy_groups"][0] == (groups, groups)
+    for nrhs, seed in ((1, 81), (3, 82)):
+        x = random_current(rwg.n, nrhs=nrhs, seed=seed)
+        ref = oaim.matvec_fft(op, x)
+        y = plan.matvec(torch.from_numpy(x).cuda(), A.AIM_FP64).cpu().numpy()
+        x32 = x.astype(np.complex64)
+        ref32 = oaim.matvec_fft(op, x32.astype(np.complex128))
+        y32 = plan.matvec(torch.from_numpy(x32).cuda(), A.AIM_MIXED).cpu().numpy()
+        for r in range(nrhs):
+            assert rel_max(y[r], ref[r]) <= 1e-10, (nrhs, r)
+            assert rel(y32[r], ref32[r]) <= 2e-5, (nrhs, r)
+            assert rel_max(y32[r], ref32[r]) <= 2e-5, (nrhs, r)
+    # the pipeline's own grids
+    c = type("C", (), {})()
+    c.op, c.k, c.pad = op, wavenumber(m.freq_hz), inf["pad"][0]
+    c.ghat = oaim.green_spectrum(c.k, op.grid, c.pad)
+    x = random_current(rwg.n, nrhs=2, seed=83)
+    refs = _reference_stages(c, x)
+    xt = torch.from_numpy(x).cuda()
+    Nx, Ny, Nz = (int(v) for v in op.grid.n)
+    occ = _occupancy(c)
+    lines = occ.any(axis=2)
+    ymask = np.zeros((Nx, Ny), dtype=bool)
+    for i in range(Nx):
+        ys = np.flatnonzero(lines[i])
+        if ys.size:
+            ymask[i, ys[0]:ys[-1] + 1] = True
+    for P, tol in ((A.AIM_FP64, 1e-12), (A.AIM_MIXED, 3e-6)):
+        for stage in (4, 5):
+            got = plan.product_stage(0, xt, stage, P).cpu().numpy()
+            r = refs[stage].reshape(got.shape)
+            msk = (np.ones(got.shape, dtype=bool) if stage == 4
+                   else np.broadcast_to(ymask.reshape(1, 1, Nx * Ny, 1), got.shape))
+            err = np.abs(got[msk] - r[msk]).max() / np.abs(r[msk]).max()
+            assert err <= tol, (P, stage, err)
+    plan.close()
+
+
+def test_pipeline_group_count_is_validated():
+    from paper_1010_1456_amd import aim as A
+
+    m = plate_mesh(1.0, 0.3e9)
+    with pytest.raises(A.AimError):
+        A.Plan([(m.verts, m.tris, m.freq_hz)], xy_groups=3)
