@@ -272,7 +272,8 @@ class Plan:
     meshes: list of (verts (nv,3) metres, tris (nt,3), freq_hz)."""
 
     def __init__(self, meshes, h_lambda=0.1, order=2, near_radius_lambda=0.3, fft_min_pad=0,
-                 mixed=True, stream=None, cfie_alpha=None, cfie_closed_only=False, xy_groups=0):
+                 mixed=True, stream=None, cfie_alpha=None, cfie_closed_only=False, xy_groups=0,
+                 flags=0):
         import torch
 
         self._torch = torch
@@ -285,8 +286,9 @@ class Plan:
         arr = (AimMesh * len(meshes))()
         for i, (v, t, f) in enumerate(meshes):
             arr[i] = _mesh_struct(v, t, f, keep)
-        p = _params(h_lambda, order, near_radius_lambda, fft_min_pad, 0 if mixed else AIM_FLAG_NO_MIXED,
-                    cfie_alpha, cfie_closed_only, xy_groups)
+        p = _params(h_lambda, order, near_radius_lambda, fft_min_pad,
+                    int(flags) | (0 if mixed else AIM_FLAG_NO_MIXED), cfie_alpha, cfie_closed_only,
+                    xy_groups)
         self._alloc = TorchAllocator(self.device)
         h = c_void_p()
         _check(L.aim_setup(arr, len(meshes), ctypes.byref(p), ctypes.byref(self._alloc.struct),
