@@ -102,9 +102,13 @@ constexpr bool thin_layout(int Pz) {
   return Pz < kGridBlock<T>;
 }
 
+// streams a multi-mesh product spreads its meshes over
+constexpr int kMaxLanes = 4;
+
 struct MeshDev {
   HostPlan hp;
   int64_t offset = 0;
+  int lane = 0;  // stream lane of this mesh's product (multi-mesh plans)
   FftPlan plan[3];
   int H[3] = {0, 0, 0};       // octant extents P_d/2 + 1
   // geometry
@@ -225,9 +229,17 @@ struct Plan {
   std::vector<MeshDev> mesh;
   std::vector<std::pair<void *, size_t>> live;  // allocations (for destroy/info)
   double device_bytes = 0;
-  // grid work buffers (per precision), grown on demand
-  void *work[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
-  size_t work_bytes[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  // grid work buffers per lane and precision, grown on demand
+  void *work[kMaxLanes][2][3] = {};
+  size_t work_bytes[kMaxLanes][2][3] = {};
+  // lanes of a multi-mesh product: the meshes are dealt to nlanes streams
+  // (lane 0 is the caller's stream, lanes 1.. the plan's own, default
+  // priority), each with its own work buffers, so that the members' products
+  // overlap; fork / join events order them with the caller's stream
+  int nlanes = 1;
+  hipStream_t lane_stream[kMaxLanes] = {};
+  hipEvent_t lane_fork = nullptr;
+  hipEvent_t lane_join[kMaxLanes] = {};
   uint64_t work_gen = 0;  // bumped whenever a grid work buffer moves (invalidates solve graphs)
   // solver buffers, stream and captured graphs, kept across solves (solver.hip)
   struct SolverState *solver = nullptr;
@@ -313,7 +325,20 @@ void copy_stage_view(const StageView &v, void *out, hipStream_t s);
 template <typename T, typename TX, typename TY>
 void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, cx<TY> *y,
                  int64_t ldy, hipStream_t s, hipEvent_t *ev = nullptr);
-void *work_buffer(Plan *pl, int prec, int which, size_t bytes, hipStream_t s);
+void *work_buffer(Plan *pl, int lane, int prec, int which, size_t bytes, hipStream_t s);
+// y = Z x over every mesh of the plan (x, y: [n_total][nrhs], leading
+// dimension n_total; c128 for AIM_FP64 and AIM_MIXED_IO64, c64 for
+// AIM_MIXED): the meshes' products run on their lanes, forked from and
+// joined back to s; with `ev` (one event set of AIM_NSTAGE + 1 per mesh) they
+// run one after the other on s instead, each event set recording its stages
+// `mesh_on` (optional, one flag per mesh): meshes flagged 0 are skipped (their
+// rows of y are left as they are)
+void matvec_plan(Plan *pl, aim_precision prec, int nrhs, const void *x, void *y, hipStream_t s,
+                 hipEvent_t *ev = nullptr, const std::vector<char> *mesh_on = nullptr);
+// deals the meshes to lanes (longest product first to the least loaded lane)
+// and creates the lanes' streams and events
+void assign_lanes(Plan *pl, const std::vector<double> &cost);
+void release_lanes(Plan *pl);
 // copies the grid buffer after far stage `stage` to out in plain layout
 template <typename T>
 void copy_far_stage(Plan *pl, MeshDev &md, int nrhs, int stage, void *out, hipStream_t s);

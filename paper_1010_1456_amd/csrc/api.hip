@@ -199,6 +199,9 @@ aim_status aim_setup(const aim_mesh *meshes, int32_t nmesh, const aim_params *p,
     pl->n_total = off;
     if (off > INT32_MAX) throw Error(AIM_ERR_ARG, "too many unknowns");
     for (int i = 0; i < nmesh; ++i) setup_mesh_device(pl.get(), pl->mesh[i], pl->setup_stream);
+    std::vector<double> cost(nmesh);
+    for (int i = 0; i < nmesh; ++i) cost[i] = model_bytes(pl->mesh[i], 8, 4);
+    assign_lanes(pl.get(), cost);
     for (int i = 0; i < nmesh; ++i) {
       const double t0 = wall_ms();
       autotune_mesh(pl.get(), pl->mesh[i], pl->setup_stream);
@@ -208,6 +211,7 @@ aim_status aim_setup(const aim_mesh *meshes, int32_t nmesh, const aim_params *p,
     HIPCHECK(hipStreamSynchronize(pl->setup_stream));
   });
   if (st != AIM_OK) {
+    release_lanes(pl.get());
     free_all(pl.get());
     return st;
   }
@@ -255,6 +259,7 @@ aim_status aim_plan_info(const aim_plan *plan, aim_info *out) {
 void aim_destroy(aim_plan *plan) {
   if (!plan) return;
   solver_release(plan);
+  release_lanes(plan);
   free_all(plan);
   delete plan;
 }
@@ -270,26 +275,15 @@ static aim_status matvec_check(aim_plan *plan, aim_precision prec, int32_t nrhs,
 }
 
 static void matvec_all(aim_plan *plan, aim_precision prec, int32_t nrhs, const void *x, void *y,
-                       hipStream_t s, hipEvent_t *ev) {
-  const int64_t ld = plan->n_total;
-  for (auto &md : plan->mesh) {
-    if (prec == AIM_FP64)
-      matvec_mesh<double, double, double>(plan, md, nrhs, (const double2 *)x + md.offset, ld,
-                                          (double2 *)y + md.offset, ld, s, ev);
-    else if (prec == AIM_MIXED)
-      matvec_mesh<float, float, float>(plan, md, nrhs, (const float2 *)x + md.offset, ld,
-                                       (float2 *)y + md.offset, ld, s, ev);
-    else
-      matvec_mesh<float, double, double>(plan, md, nrhs, (const double2 *)x + md.offset, ld,
-                                         (double2 *)y + md.offset, ld, s, ev);
-  }
+                       hipStream_t s) {
+  matvec_plan(plan, prec, nrhs, x, y, s);
 }
 
 aim_status aim_matvec(aim_plan *plan, aim_precision prec, int32_t nrhs, const void *x, void *y,
                       void *hip_stream) {
   aim_status st = matvec_check(plan, prec, nrhs, x, y);
   if (st != AIM_OK) return st;
-  return guarded([&] { matvec_all(plan, prec, nrhs, x, y, (hipStream_t)hip_stream, nullptr); });
+  return guarded([&] { matvec_all(plan, prec, nrhs, x, y, (hipStream_t)hip_stream); });
 }
 
 aim_status aim_matvec_timed(aim_plan *plan, aim_precision prec, int32_t nrhs, const void *x,
@@ -305,23 +299,8 @@ aim_status aim_matvec_timed(aim_plan *plan, aim_precision prec, int32_t nrhs, co
   std::vector<hipEvent_t> ev((size_t)nrep * nm * (AIM_NSTAGE + 1), nullptr);
   aim_status r = guarded([&] {
     for (auto &e : ev) HIPCHECK(hipEventCreate(&e));
-    const int64_t ld = plan->n_total;
-    for (int rep = 0; rep < nrep; ++rep) {
-      int mi = 0;
-      for (auto &md : plan->mesh) {
-        hipEvent_t *e = &ev[((size_t)rep * nm + mi) * (AIM_NSTAGE + 1)];
-        if (prec == AIM_FP64)
-          matvec_mesh<double, double, double>(plan, md, nrhs, (const double2 *)x + md.offset, ld,
-                                              (double2 *)y + md.offset, ld, s, e);
-        else if (prec == AIM_MIXED)
-          matvec_mesh<float, float, float>(plan, md, nrhs, (const float2 *)x + md.offset, ld,
-                                           (float2 *)y + md.offset, ld, s, e);
-        else
-          matvec_mesh<float, double, double>(plan, md, nrhs, (const double2 *)x + md.offset, ld,
-                                             (double2 *)y + md.offset, ld, s, e);
-        ++mi;
-      }
-    }
+    for (int rep = 0; rep < nrep; ++rep)
+      matvec_plan(plan, prec, nrhs, x, y, s, &ev[(size_t)rep * nm * (AIM_NSTAGE + 1)]);
     HIPCHECK(hipStreamSynchronize(s));
     double acc[AIM_NSTAGE] = {0};
     for (size_t g = 0; g < (size_t)nrep * nm; ++g)
@@ -356,14 +335,14 @@ aim_status aim_matvec_graph_timed(aim_plan *plan, aim_precision prec, int32_t nr
   hipGraphExec_t ex = nullptr;
   aim_status r = guarded([&] {
     // one direct product first: work buffers exist before the capture
-    matvec_all(plan, prec, nrhs, x, y, s, nullptr);
+    matvec_all(plan, prec, nrhs, x, y, s);
     HIPCHECK(hipStreamSynchronize(s));
     HIPCHECK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
     HIPCHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     try {
-      for (int i = 0; i < nrep; ++i) matvec_all(plan, prec, nrhs, x, y, cs, nullptr);
+      for (int i = 0; i < nrep; ++i) matvec_all(plan, prec, nrhs, x, y, cs);
     } catch (...) {
       (void)hipStreamEndCapture(cs, &g);
       throw;

@@ -373,13 +373,15 @@ static cx<T> *src_buffer(Plan *pl, MeshDev &md, size_t bytes, int layout, hipStr
   return p;
 }
 
-void *work_buffer(Plan *pl, int prec, int which, size_t bytes, hipStream_t s) {
-  if (pl->work_bytes[prec][which] < bytes) {
-    if (pl->work[prec][which]) dev_free(pl, pl->work[prec][which]);
-    pl->work[prec][which] = nullptr;
-    pl->work_bytes[prec][which] = 0;
-    pl->work[prec][which] = dev_alloc(pl, bytes);
-    pl->work_bytes[prec][which] = bytes;
+void *work_buffer(Plan *pl, int lane, int prec, int which, size_t bytes, hipStream_t s) {
+  void *(&work)[3] = pl->work[lane][prec];
+  size_t(&have)[3] = pl->work_bytes[lane][prec];
+  if (have[which] < bytes) {
+    if (work[which]) dev_free(pl, work[which]);
+    work[which] = nullptr;
+    have[which] = 0;
+    work[which] = dev_alloc(pl, bytes);
+    have[which] = bytes;
     ++pl->work_gen;
     if (which == 0) {
       // the propagated fields: the inverse z pass writes the occupied lines
@@ -388,16 +390,16 @@ void *work_buffer(Plan *pl, int prec, int which, size_t bytes, hipStream_t s) {
       if (prec == 0) {
         const int64_t n = (int64_t)(bytes / sizeof(double2));
         hipLaunchKernelGGL((k_zero<double>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                           (double2 *)pl->work[prec][which], n);
+                           (double2 *)work[which], n);
       } else {
         const int64_t n = (int64_t)(bytes / sizeof(float2));
         hipLaunchKernelGGL((k_zero<float>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                           (float2 *)pl->work[prec][which], n);
+                           (float2 *)work[which], n);
       }
       LAUNCHCHECK();
     }
   }
-  return pl->work[prec][which];
+  return work[which];
 }
 
 template <typename T, typename TX>
@@ -437,8 +439,8 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     // the interpolation: the plane alone, g0 = [F][Nx][Ny], 2-D propagation
     // (y passes, x pass with the 2-D spectrum)
     const int64_t A1 = (int64_t)Nx * Ny, V2 = (int64_t)Nx * Py;
-    cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * A1, s);
-    cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2, s);
+    cx<T> *g0 = (cx<T> *)work_buffer(pl, md.lane, prec, 0, sizeof(cx<T>) * F * A1, s);
+    cx<T> *g2 = (cx<T> *)work_buffer(pl, md.lane, prec, 2, sizeof(cx<T>) * F * V2, s);
     cx<T> *gs = src_buffer<T>(pl, md, sizeof(cx<T>) * F * A1, 2, s);
     mark(0);
     const int64_t no = md.n_plane_occ;
@@ -476,9 +478,9 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     // g2 [F][Pz][Nx][Py], no row padding; the y lines are contiguous, the x
     // pass tiles consecutive ky
     const int64_t A1 = (int64_t)Nx * Ny, V1 = Pz * A1, V2 = (int64_t)Pz * Nx * Py;
-    cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * V0, s);
-    cx<T> *g1 = (cx<T> *)work_buffer(pl, prec, 1, sizeof(cx<T>) * F * V1, s);
-    cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2, s);
+    cx<T> *g0 = (cx<T> *)work_buffer(pl, md.lane, prec, 0, sizeof(cx<T>) * F * V0, s);
+    cx<T> *g1 = (cx<T> *)work_buffer(pl, md.lane, prec, 1, sizeof(cx<T>) * F * V1, s);
+    cx<T> *g2 = (cx<T> *)work_buffer(pl, md.lane, prec, 2, sizeof(cx<T>) * F * V2, s);
     cx<T> *gs = src_buffer<T>(pl, md, sizeof(cx<T>) * F * V0, 1, s);
     mark(0);
     if (md.n_occ > 0) {
@@ -529,9 +531,9 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
   const int Pzs = (Pz + blk - 1) / blk * blk;  // z rows padded to 128-byte multiples
   const int64_t V1 = (int64_t)Nx * Ny * Pzs;
   const int64_t V2 = (int64_t)Nx * Py * ((Pz + blk - 1) / blk * blk);  // kz-blocked
-  cx<T> *g0 = (cx<T> *)work_buffer(pl, prec, 0, sizeof(cx<T>) * F * V0, s);
-  cx<T> *g1 = (cx<T> *)work_buffer(pl, prec, 1, sizeof(cx<T>) * F * V1, s);
-  cx<T> *g2 = (cx<T> *)work_buffer(pl, prec, 2, sizeof(cx<T>) * F * V2, s);
+  cx<T> *g0 = (cx<T> *)work_buffer(pl, md.lane, prec, 0, sizeof(cx<T>) * F * V0, s);
+  cx<T> *g1 = (cx<T> *)work_buffer(pl, md.lane, prec, 1, sizeof(cx<T>) * F * V1, s);
+  cx<T> *g2 = (cx<T> *)work_buffer(pl, md.lane, prec, 2, sizeof(cx<T>) * F * V2, s);
   const fftk::LineMap m1 = fftk::plain_map((int64_t)Ny * Pzs, Pzs);
   const fftk::LineMap m2 = fftk::blocked_map(V2, Nx, Py, blk);
   cx<T> *gz = g1;  // forward z output, forward y input
@@ -638,7 +640,7 @@ void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, 
   const HostPlan &h = md.hp;
   const int prec = sizeof(T) == 8 ? 0 : 1;
   far_stages<T, TX>(pl, md, nrhs, x, ldx, 6, s, ev);
-  const cx<T> *phi = (const cx<T> *)pl->work[prec][0];
+  const cx<T> *phi = (const cx<T> *)pl->work[md.lane][prec][0];
   const bool plane = md.planar_z >= 0;  // fields on the scatterer's grid plane only
   const int64_t nf = 4 * (int64_t)nrhs;  // fields per node of the interleaved grid
   const int rows_per_block = 8;
@@ -674,6 +676,78 @@ void matvec_mesh(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, 
   if (ev) HIPCHECK(hipEventRecord(ev[7], s));
 }
 
+void assign_lanes(Plan *pl, const std::vector<double> &cost) {
+  const int K = std::min(pl->nmesh, kMaxLanes);
+  pl->nlanes = K;
+  if (K > 1) {
+    HIPCHECK(hipEventCreateWithFlags(&pl->lane_fork, hipEventDisableTiming));
+    for (int l = 1; l < K; ++l) {
+      HIPCHECK(hipStreamCreateWithFlags(&pl->lane_stream[l], hipStreamNonBlocking));
+      HIPCHECK(hipEventCreateWithFlags(&pl->lane_join[l], hipEventDisableTiming));
+    }
+  }
+  std::vector<int> order(pl->nmesh);
+  for (int i = 0; i < pl->nmesh; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<double> load(K, 0.0);
+  for (int i : order) {
+    int l = 0;
+    for (int j = 1; j < K; ++j)
+      if (load[j] < load[l]) l = j;
+    pl->mesh[i].lane = l;
+    load[l] += cost[i];
+  }
+}
+
+void release_lanes(Plan *pl) {
+  for (int l = 1; l < kMaxLanes; ++l) {
+    if (pl->lane_stream[l]) {
+      (void)hipStreamSynchronize(pl->lane_stream[l]);
+      (void)hipStreamDestroy(pl->lane_stream[l]);
+    }
+    if (pl->lane_join[l]) (void)hipEventDestroy(pl->lane_join[l]);
+    pl->lane_stream[l] = nullptr;
+    pl->lane_join[l] = nullptr;
+  }
+  if (pl->lane_fork) (void)hipEventDestroy(pl->lane_fork);
+  pl->lane_fork = nullptr;
+  pl->nlanes = 1;
+}
+
+void matvec_plan(Plan *pl, aim_precision prec, int nrhs, const void *x, void *y, hipStream_t s,
+                 hipEvent_t *ev, const std::vector<char> *mesh_on) {
+  const int64_t ld = pl->n_total;
+  const bool lanes = pl->nlanes > 1 && !ev;
+  if (lanes) {
+    HIPCHECK(hipEventRecord(pl->lane_fork, s));
+    for (int l = 1; l < pl->nlanes; ++l) HIPCHECK(hipStreamWaitEvent(pl->lane_stream[l], pl->lane_fork, 0));
+  }
+  int mi = 0;
+  for (auto &md : pl->mesh) {
+    if (mesh_on && !(*mesh_on)[mi]) {
+      ++mi;
+      continue;
+    }
+    const hipStream_t st = (lanes && md.lane > 0) ? pl->lane_stream[md.lane] : s;
+    hipEvent_t *e = ev ? ev + (size_t)mi * (AIM_NSTAGE + 1) : nullptr;
+    if (prec == AIM_FP64)
+      matvec_mesh<double, double, double>(pl, md, nrhs, (const double2 *)x + md.offset, ld,
+                                          (double2 *)y + md.offset, ld, st, e);
+    else if (prec == AIM_MIXED)
+      matvec_mesh<float, float, float>(pl, md, nrhs, (const float2 *)x + md.offset, ld,
+                                       (float2 *)y + md.offset, ld, st, e);
+    else
+      matvec_mesh<float, double, double>(pl, md, nrhs, (const double2 *)x + md.offset, ld,
+                                         (double2 *)y + md.offset, ld, st, e);
+    ++mi;
+  }
+  if (lanes)
+    for (int l = 1; l < pl->nlanes; ++l) {
+      HIPCHECK(hipEventRecord(pl->lane_join[l], pl->lane_stream[l]));
+      HIPCHECK(hipStreamWaitEvent(s, pl->lane_join[l], 0));
+    }
+}
+
 template <typename T>
 void copy_far_stage(Plan *pl, MeshDev &md, int nrhs, int stage, void *out, hipStream_t s) {
   const HostPlan &h = md.hp;
@@ -687,7 +761,7 @@ void copy_far_stage(Plan *pl, MeshDev &md, int nrhs, int stage, void *out, hipSt
     const int64_t A = (stage == 3 || stage == 4) ? (int64_t)Nx * Py : (int64_t)Nx * Ny;
     const int64_t tot = F * A * Pz;
     hipLaunchKernelGGL((k_kz_inner<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                       (const cx<T> *)pl->work[prec][(stage == 3 || stage == 4) ? 2 : 1],
+                       (const cx<T> *)pl->work[md.lane][prec][(stage == 3 || stage == 4) ? 2 : 1],
                        (cx<T> *)out, F, A, Pz);
     LAUNCHCHECK();
     return;
@@ -695,18 +769,18 @@ void copy_far_stage(Plan *pl, MeshDev &md, int nrhs, int stage, void *out, hipSt
   if (stage == 3 || stage == 4) {
     const int64_t tot = F * Nx * Py * Pz;
     hipLaunchKernelGGL((k_unblock<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                       (const cx<T> *)pl->work[prec][2], (cx<T> *)out, F, Nx, Py, Pz, blk, V2);
+                       (const cx<T> *)pl->work[md.lane][prec][2], (cx<T> *)out, F, Nx, Py, Pz, blk, V2);
     LAUNCHCHECK();
     return;
   }
   if (stage == 2 || stage == 5) {  // drop the row padding
     const int Pzs = (Pz + blk - 1) / blk * blk;
-    HIPCHECK(hipMemcpy2DAsync(out, sizeof(cx<T>) * Pz, pl->work[prec][1], sizeof(cx<T>) * Pzs,
+    HIPCHECK(hipMemcpy2DAsync(out, sizeof(cx<T>) * Pz, pl->work[md.lane][prec][1], sizeof(cx<T>) * Pzs,
                               sizeof(cx<T>) * Pz, (size_t)(F * Nx * Ny), hipMemcpyDeviceToDevice, s));
     return;
   }
   // stage 1: the projected source grid; stage 6: the propagated fields
-  HIPCHECK(hipMemcpyAsync(out, stage == 1 ? md.src[prec] : pl->work[prec][0],
+  HIPCHECK(hipMemcpyAsync(out, stage == 1 ? md.src[prec] : pl->work[md.lane][prec][0],
                           sizeof(cx<T>) * F * Nx * Ny * Nz, hipMemcpyDeviceToDevice, s));
 }
 template void copy_far_stage<double>(Plan *, MeshDev &, int, int, void *, hipStream_t);

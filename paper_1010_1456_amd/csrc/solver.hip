@@ -261,16 +261,17 @@ struct Ctx {
   int S;  // systems = nmesh * R
   int64_t ld;
   double2 *dinv;
+  // meshes with a system still iterating: the Arnoldi steps skip the others'
+  // products and Gram-Schmidt work (their systems are inactive, so nothing
+  // reads what those steps would have written); empty = every mesh
+  std::vector<char> on;
+  bool mesh_on(int mi) const { return on.empty() || on[mi]; }
 };
 
 // y = A x with the operator of the given precision on c128 vectors
 void apply(Ctx &c, aim_precision prec, const double2 *x, double2 *y) {
-  for (auto &md : c.pl->mesh) {
-    if (prec == AIM_FP64)
-      matvec_mesh<double, double, double>(c.pl, md, c.R, x + md.offset, c.ld, y + md.offset, c.ld, c.s);
-    else
-      matvec_mesh<float, double, double>(c.pl, md, c.R, x + md.offset, c.ld, y + md.offset, c.ld, c.s);
-  }
+  matvec_plan(c.pl, prec == AIM_FP64 ? AIM_FP64 : AIM_MIXED_IO64, c.R, x, y, c.s, nullptr,
+              c.on.empty() ? nullptr : &c.on);
 }
 
 // nrm[s] = |v_s|^2 for every system, on the device (partials, fixed order)
@@ -432,7 +433,8 @@ struct SolverState {
   std::vector<void *> bufs;
   hipStream_t stream = nullptr;
   hipEvent_t entry = nullptr;
-  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;  // (precision, j0, j1)
+  // (precision, j0, j1, meshes still iterating as bits)
+  std::map<std::tuple<int, int, int, uint32_t>, hipGraphExec_t> graphs;
   uint64_t gen = 0;       // plan work-buffer generation the graphs were captured with
   bool warm[2] = {false, false};  // a direct step of this precision ran on these buffers
 };
@@ -511,6 +513,10 @@ void arnoldi_step(Ctx &c, aim_precision prec, Work &wk, int j, int m) {
     double2 *h = pass == 0 ? wk.h1 : wk.h2;
     int mi = 0;
     for (auto &md : c.pl->mesh) {
+      if (!c.mesh_on(mi)) {
+        ++mi;
+        continue;
+      }
       const int64_t nb = dot_parts(md.hp.n) / kDotWaves;
       hipLaunchKernelGGL(k_dots_part, dim3((unsigned)nb, R, nblk(j + 1, kGroup)),
                          dim3(64 * kDotWaves), 0, c.s, wk.V, wk.w, ld, vstride, md.offset,
@@ -527,6 +533,10 @@ void arnoldi_step(Ctx &c, aim_precision prec, Work &wk, int j, int m) {
   }
   int mi = 0;
   for (auto &md : c.pl->mesh) {
+    if (!c.mesh_on(mi)) {
+      ++mi;
+      continue;
+    }
     const unsigned nb = red_blocks(md.hp.n);
     hipLaunchKernelGGL(k_norm2_part, dim3(nb, R), dim3(kRed), 0, c.s, wk.w, ld, md.offset,
                        md.offset + md.hp.n, mi * R, wk.npart);
@@ -548,7 +558,10 @@ void run_segment_graph(Plan *pl, SolverState &st, Ctx &c, aim_precision prec, in
     drop_graphs(st);
     st.gen = pl->work_gen;
   }
-  const auto key = std::make_tuple((int)prec, j0, j1);
+  uint32_t bits = 0;
+  for (int i = 0; i < c.pl->nmesh; ++i)
+    if (c.mesh_on(i)) bits |= 1u << i;
+  const auto key = std::make_tuple((int)prec, j0, j1, bits);
   auto it = st.graphs.find(key);
   if (it == st.graphs.end()) {
     HIPCHECK(hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal));
@@ -594,7 +607,17 @@ int gmres_run(Ctx &c, SolverState &st, aim_precision prec, bool graphs, const do
   bool first_cycle = true;
   std::vector<int> act(S), itd(S), jendh(S, m);
   HIPCHECK(hipMemcpyAsync(wk.dev.its, its.data(), sizeof(int) * S, hipMemcpyHostToDevice, c.s));
+  // meshes with a system for which flag[s] is set
+  auto meshes_of = [&](const auto &flag) {
+    std::vector<char> on(c.pl->nmesh, 0);
+    for (int s = 0; s < S; ++s)
+      if (flag[s]) on[s / R] = 1;
+    return on;
+  };
+  std::vector<char> notdone(S);
   while (true) {
+    for (int s = 0; s < S; ++s) notdone[s] = !done[s];
+    c.on = meshes_of(notdone);
     // residual of the current iterate: r = rhs - A d (rhs itself on the first cycle)
     if (first_cycle) {
       HIPCHECK(hipMemcpyAsync(wk.w, rhs, sizeof(double2) * cnt, hipMemcpyDeviceToDevice, c.s));
@@ -645,6 +668,7 @@ int gmres_run(Ctx &c, SolverState &st, aim_precision prec, bool graphs, const do
     // segments of kCheckEvery steps between polls of the active flags; a full
     // segment (or the cycle's last) is a graph once this precision has run
     // directly on the current buffers (so no buffer is allocated in a capture)
+    c.on = meshes_of(act);
     for (int j = 0; j < m && total < max_iter;) {
       const int j1 = std::min({j + kCheckEvery, m, j + (max_iter - total)});
       const bool whole = (j1 - j == kCheckEvery) || j1 == m;
@@ -662,6 +686,7 @@ int gmres_run(Ctx &c, SolverState &st, aim_precision prec, bool graphs, const do
       bool any = false;
       for (int s = 0; s < S; ++s) any |= (bool)act[s];
       if (!any) break;
+      c.on = meshes_of(act);
     }
     // d += D^-1 V y, y = H^-1 g per system (systems done before the cycle: jend = 0)
     hipLaunchKernelGGL(k_backsub, dim3(S), dim3(64), sizeof(double2) * (size_t)m, c.s, wk.dev,
@@ -683,6 +708,7 @@ int gmres_run(Ctx &c, SolverState &st, aim_precision prec, bool graphs, const do
   HIPCHECK(hipMemcpyAsync(itd.data(), wk.dev.its, sizeof(int) * S, hipMemcpyDeviceToHost, c.s));
   HIPCHECK(hipStreamSynchronize(c.s));
   for (int s = 0; s < S; ++s) its[s] = itd[s];
+  c.on.clear();  // later products (the outer residual) cover every mesh
   return total;
 }
 
