@@ -563,6 +563,8 @@ def main(argv=None):
     ap.add_argument("--xy-groups", type=int, default=0, choices=[0, 1, 2, 4],
                     help="field groups of the pipelined y / x / y passes (0: chosen at set-up)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-efie-line", action="store_true",
+                    help="skip the EFIE reference line of a CFIE sphere workload")
     ap.add_argument("--solve-iters", type=int, default=3000,
                     help="GMRES iteration cap of the solve comparison (0 skips it)")
     ap.add_argument("--calibrate", action="store_true",
@@ -711,7 +713,7 @@ def main(argv=None):
     if args.solve_iters > 0:
         out["solve"] = solve_compare(plan, A, mesh, args.workload, args.solve_iters, alpha)
     plan.close()
-    if args.workload.startswith("sphere") and alpha is not None:
+    if args.workload.startswith("sphere") and alpha is not None and not args.no_efie_line:
         # the EFIE operator on the same sphere, for reference: product rate and
         # the iterations its (mixed) solve needs to reach 1e-4, or the stall
         log("[bench] EFIE plan (reference line)")

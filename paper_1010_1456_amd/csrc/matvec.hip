@@ -885,12 +885,17 @@ void autotune_mesh(Plan *pl, MeshDev &md, hipStream_t s) {
         md.xy_groups[prec] = forced;
         continue;
       }
-      float best = 0;
+      // the pipeline must beat the sequential passes by a clear margin: the
+      // set-up times a few products of one right-hand side, and differences
+      // of a few percent there are within run-to-run spread
+      float best = 0, sequential = 0;
       int choice = 1;
       for (int g : {1, 2, 4}) {
         md.xy_groups[prec] = g;
         const float ms = time_stages(prec, 6);
-        if (g == 1 || ms < best) {
+        if (g == 1) {
+          best = sequential = ms;
+        } else if (ms < best && ms < 0.97f * sequential) {
           best = ms;
           choice = g;
         }
