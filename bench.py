@@ -562,6 +562,8 @@ def main(argv=None):
                     help="the EFIE on every scatterer (closed ones too)")
     ap.add_argument("--xy-groups", type=int, default=0, choices=[0, 1, 2, 4],
                     help="field groups of the pipelined y / x / y passes (0: chosen at set-up)")
+    ap.add_argument("--tile-rows", type=int, default=0, choices=[0, 64, 128],
+                    help="bytes of grid lines per x / y pass tile (0: chosen at set-up)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-efie-line", action="store_true",
                     help="skip the EFIE reference line of a CFIE sphere workload")
@@ -617,7 +619,8 @@ def main(argv=None):
         t0 = time.perf_counter()
         pl = A.Plan([(m.verts, m.tris, m.freq_hz) for m in meshes], h_lambda=cfg["h_lambda"],
                     order=cfg["order"], near_radius_lambda=cfg["near_radius_lambda"],
-                    cfie_alpha=a, cfie_closed_only=True, xy_groups=args.xy_groups)
+                    cfie_alpha=a, cfie_closed_only=True, xy_groups=args.xy_groups,
+                    tile_rows=args.tile_rows)
         torch.cuda.synchronize()
         return pl, time.perf_counter() - t0
 
@@ -625,7 +628,8 @@ def main(argv=None):
     info = plan.info()
     n = info["n_total"]
     log(f"[bench] set-up {setup_s:.2f} s: N={n} grid={info['grid'][0]} pad={info['pad'][0]} "
-        f"nnz={info['nnz_total']} cfie={info['cfie_alpha']} xy_groups={info['xy_groups']}")
+        f"nnz={info['nnz_total']} cfie={info['cfie_alpha']} xy_groups={info['xy_groups']} "
+        f"tile_bytes={info['tile_bytes']}")
     R = args.nrhs if args.nrhs is not None else (16 if args.workload == "batch6" else 1)
     x = torch.from_numpy(random_current(n, nrhs=R, seed=7)).cuda()
     y = torch.empty_like(x)
@@ -671,6 +675,7 @@ def main(argv=None):
             "fused_projection": info["fused_projection"][0][1],
             "gather_nodes_per_wave": info["gather_npw"][0][1],
             "xy_pipeline_groups": info["xy_groups"][0][1],
+            "tile_bytes_x_y": info["tile_bytes"][0][1],
         },
         "roofline": {
             "bound": "hbm",

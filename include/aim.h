@@ -83,11 +83,15 @@ typedef struct {
  * fft_min_pad         0: FFT length per dimension = smallest supported
  *                     length >= 2 N_d - 1; otherwise a lower bound on it
  * flags               AIM_FLAG_* below
- * xy_groups           0: the set-up picks by timing how many field groups the
- *                     forward y, x and inverse y passes are pipelined over
- *                     (aim_info.xy_groups); 1, 2 or 4: that many wherever the
- *                     pipeline applies (for tests and measurements); other
- *                     values give AIM_ERR_ARG
+ * tuning              kernel variants the set-up would otherwise pick by
+ *                     timing (for tests and measurements; 0 = pick all):
+ *                     bits 0-7  field groups the forward y, x and inverse y
+ *                               passes are pipelined over (aim_info.xy_groups):
+ *                               0 (pick), 1, 2 or 4;
+ *                     bits 8-15 tile rows of the x and strided y passes
+ *                               (aim_info.tile_bytes): 0 (pick), 1 (128-byte
+ *                               rows), 2 (64-byte rows);
+ *                     other values give AIM_ERR_ARG
  * cfie_alpha          with AIM_FLAG_CFIE: the combination parameter alpha in
  *                     [0, 1] of alpha EFIE + (1 - alpha) eta MFIE (the paper
  *                     uses 0.6 for its closed scatterers, Section 2.2);
@@ -98,7 +102,7 @@ typedef struct {
   int32_t fft_min_pad;
   double near_radius_lambda;
   int32_t flags;
-  int32_t xy_groups;
+  int32_t tuning;
   double cfie_alpha;
 } aim_params;
 
@@ -195,6 +199,10 @@ typedef struct {
                                            x pass of one group beside the y passes of others in
                                            one launch (1: one pass after the other; chosen by
                                            timing at set-up) */
+  int32_t tile_bytes[AIM_MAX_MESH][2][2]; /* [mesh][0 FP64, 1 mixed][0 x pass, 1 strided y
+                                           passes]: bytes of consecutive grid lines (128 or 64)
+                                           in one work-group's tile (chosen by timing at
+                                           set-up) */
 } aim_info;
 
 /* GMRES options. restart m (<= 200), relative-residual tolerance on

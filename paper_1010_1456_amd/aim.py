@@ -65,7 +65,7 @@ class AimMesh(ctypes.Structure):
 
 class AimParams(ctypes.Structure):
     _fields_ = [("h_lambda", c_double), ("order", c_int32), ("fft_min_pad", c_int32),
-                ("near_radius_lambda", c_double), ("flags", c_int32), ("xy_groups", c_int32),
+                ("near_radius_lambda", c_double), ("flags", c_int32), ("tuning", c_int32),
                 ("cfie_alpha", c_double)]
 
 
@@ -91,7 +91,8 @@ class AimInfo(ctypes.Structure):
                 ("fused_projection", (c_int32 * 2) * M), ("planar_z", c_int32 * M),
                 ("device_bytes", c_double), ("setup_ms", (c_double * AIM_NSETUP) * M),
                 ("cfie_alpha", c_double * M), ("occ_nodes", c_int64 * M), ("occ_lines", c_int64 * M),
-                ("gather_npw", (c_int32 * 2) * M), ("xy_groups", (c_int32 * 2) * M)]
+                ("gather_npw", (c_int32 * 2) * M), ("xy_groups", (c_int32 * 2) * M),
+                ("tile_bytes", ((c_int32 * 2) * 2) * M)]
 
 
 class AimSolveOpts(ctypes.Structure):
@@ -195,11 +196,15 @@ def _mesh_struct(verts, tris, freq_hz, keep):
 
 
 def _params(h_lambda, order, near_radius_lambda, fft_min_pad=0, flags=0, cfie_alpha=None,
-            cfie_closed_only=False, xy_groups=0):
+            cfie_closed_only=False, xy_groups=0, tile_rows=0):
+    """tile_rows: 0 (chosen at set-up), 128 or 64 bytes of grid lines per
+    tile of the x and strided y passes."""
     if cfie_alpha is not None:
         flags |= AIM_FLAG_CFIE_CLOSED if cfie_closed_only else AIM_FLAG_CFIE
+    rows = {0: 0, 128: 1, 64: 2}[int(tile_rows)]
     return AimParams(float(h_lambda), int(order), int(fft_min_pad), float(near_radius_lambda),
-                     int(flags), int(xy_groups), float(cfie_alpha) if cfie_alpha is not None else 0.0)
+                     int(flags), int(xy_groups) | (rows << 8),
+                     float(cfie_alpha) if cfie_alpha is not None else 0.0)
 
 
 def _waves(waves):
@@ -273,7 +278,7 @@ class Plan:
 
     def __init__(self, meshes, h_lambda=0.1, order=2, near_radius_lambda=0.3, fft_min_pad=0,
                  mixed=True, stream=None, cfie_alpha=None, cfie_closed_only=False, xy_groups=0,
-                 flags=0):
+                 flags=0, tile_rows=0):
         import torch
 
         self._torch = torch
@@ -288,7 +293,7 @@ class Plan:
             arr[i] = _mesh_struct(v, t, f, keep)
         p = _params(h_lambda, order, near_radius_lambda, fft_min_pad,
                     int(flags) | (0 if mixed else AIM_FLAG_NO_MIXED), cfie_alpha, cfie_closed_only,
-                    xy_groups)
+                    xy_groups, tile_rows)
         self._alloc = TorchAllocator(self.device)
         h = c_void_p()
         _check(L.aim_setup(arr, len(meshes), ctypes.byref(p), ctypes.byref(self._alloc.struct),
@@ -331,7 +336,8 @@ class Plan:
             occ_nodes=[inf.occ_nodes[i] for i in range(nm)],
             occ_lines=[inf.occ_lines[i] for i in range(nm)],
             gather_npw=[tuple(inf.gather_npw[i]) for i in range(nm)],
-            xy_groups=[tuple(inf.xy_groups[i]) for i in range(nm)])
+            xy_groups=[tuple(inf.xy_groups[i]) for i in range(nm)],
+            tile_bytes=[tuple(tuple(inf.tile_bytes[i][q]) for q in range(2)) for i in range(nm)])
 
     def _stream(self, stream):
         s = stream if stream is not None else self._torch.cuda.current_stream()

@@ -183,6 +183,10 @@ struct MeshDev {
   // field groups of the pipelined y / x / y passes per precision (1: the
   // three passes one after the other), chosen by timing at set-up
   int xy_groups[2] = {1, 1};
+  // bytes of consecutive lines per work-group tile (128 or 64) of the x pass
+  // and of the strided y passes, per precision; chosen by timing at set-up
+  int x_row[2] = {128, 128};
+  int y_row[2] = {128, 128};
   double setup_ms[AIM_NSETUP] = {0, 0, 0, 0, 0};  // wall time per set-up phase
   // combined field only: curl weights W[n][e][u] = int (t_n x grad l_u)_e,
   // t_n = f_n x n (the MFIE part is interpolated from the vector potential's
@@ -264,10 +268,11 @@ struct ContigMap;
                        bool inverse, const V *tw, hipStream_t s);                                \
   void fft_pass_strided(const V *in, V *out, const FftPlan &pl, int n_in, int n_out,             \
                         int64_t outer, int64_t inner, const fftk::LineMap &imap,                 \
-                        const fftk::LineMap &omap, bool inverse, const V *tw, hipStream_t s);    \
+                        const fftk::LineMap &omap, bool inverse, const V *tw, int row_bytes,     \
+                        hipStream_t s);                                                          \
   void fft_mid_pass(V *data, const FftPlan &pl, int n_x, int nfield, int Py, int Pz, int Hx,     \
                     int Hy, int Hz, const V *ghat, const V *tw, int blk, int64_t fstride,        \
-                    hipStream_t s);
+                    int row_bytes, hipStream_t s);
 AIM_DECLARE_FFT(float2)
 AIM_DECLARE_FFT(double2)
 #undef AIM_DECLARE_FFT

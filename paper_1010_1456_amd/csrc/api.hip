@@ -173,8 +173,11 @@ aim_status aim_setup(const aim_mesh *meshes, int32_t nmesh, const aim_params *p,
   if (!meshes || !p) return fail(AIM_ERR_ARG, "NULL meshes or params");
   if (nmesh < 1 || nmesh > AIM_MAX_MESH) return fail(AIM_ERR_ARG, "nmesh out of range");
   if (alloc && (!alloc->alloc || !alloc->free)) return fail(AIM_ERR_ARG, "incomplete allocator");
-  if (p->xy_groups != 0 && p->xy_groups != 1 && p->xy_groups != 2 && p->xy_groups != 4)
-    return fail(AIM_ERR_ARG, "xy_groups must be 0, 1, 2 or 4");
+  {
+    const int g = p->tuning & 0xff, t = (p->tuning >> 8) & 0xff;
+    if ((p->tuning >> 16) != 0 || (g != 0 && g != 1 && g != 2 && g != 4) || t > 2)
+      return fail(AIM_ERR_ARG, "tuning: pipeline groups 0, 1, 2 or 4; tile rows 0, 1 or 2");
+  }
   std::unique_ptr<aim_plan> pl(new aim_plan());
   if (alloc) {
     pl->alloc = *alloc;
@@ -250,6 +253,10 @@ aim_status aim_plan_info(const aim_plan *plan, aim_info *out) {
     out->gather_npw[i][1] = md.gather_npw[1];
     out->xy_groups[i][0] = md.xy_groups[0];
     out->xy_groups[i][1] = md.xy_groups[1];
+    for (int q = 0; q < 2; ++q) {
+      out->tile_bytes[i][q][0] = md.x_row[q];
+      out->tile_bytes[i][q][1] = md.y_row[q];
+    }
     for (int j = 0; j < AIM_NSETUP; ++j) out->setup_ms[i][j] = md.setup_ms[j];
   }
   out->device_bytes = plan->device_bytes;

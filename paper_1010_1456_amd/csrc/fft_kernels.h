@@ -68,23 +68,23 @@ constexpr int tile_rows(int row_bytes) {
     B /= 2;
   return B;
 }
-template <typename T, class PC>
+// Strided (y) and x passes: a tile spans ROW bytes of consecutive lines, 128
+// (one cache line) or 64; the set-up picks per mesh and precision by timing.
+template <typename T, class PC, int ROW = 128>
 constexpr int tile_strided() {
-  return tile_rows<T, PC>(128);  // 128-byte rows (64-byte rows measured slower)
+  return tile_rows<T, PC>(ROW);
 }
-template <typename T, class PC>
+template <typename T, class PC, int ROW = 128>
 constexpr int threads_strided() {
-  return round_up_c(PC::maxnb() * tile_strided<T, PC>(), 64);
+  return round_up_c(PC::maxnb() * tile_strided<T, PC, ROW>(), 64);
 }
-// x pass: lines per work-group (128-byte rows; 64- and 256-byte rows measured
-// slower on the 324-point plan)
-template <typename T, class PC>
+template <typename T, class PC, int ROW = 128>
 constexpr int tile_mid() {
-  return tile_rows<T, PC>(128);
+  return tile_rows<T, PC>(ROW);
 }
-template <typename T, class PC>
+template <typename T, class PC, int ROW = 128>
 constexpr int threads_mid() {
-  return round_up_c(PC::maxnb() * tile_mid<T, PC>(), 64);
+  return round_up_c(PC::maxnb() * tile_mid<T, PC, ROW>(), 64);
 }
 template <typename T, class PC>
 constexpr int tile_contig() {
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__((threads_contig<T, PC>()))
 
 // One work-group of a strided pass: tile vb = o ntile + (c0 / B) covers the
 // B lines (o, c0 .. c0 + B - 1).
-template <typename T, bool INV, bool PR, class PC>
+template <typename T, bool INV, bool PR, class PC, int ROW = 128>
 __device__ __forceinline__ void strided_body(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
                                              int n_in, int n_out, int64_t inner, int ntile,
                                              const LineMap &imap, const LineMap &omap,
@@ -193,7 +193,7 @@ __device__ __forceinline__ void strided_body(const cx<T> *__restrict__ in, cx<T>
   extern __shared__ unsigned char smem_raw[];
   V *lds = reinterpret_cast<V *>(smem_raw);
   constexpr int P = PC::P;
-  constexpr int B = tile_strided<T, PC>();
+  constexpr int B = tile_strided<T, PC, ROW>();
   const int64_t o = vb / ntile;
   const int64_t c0 = (vb % ntile) * B;
   const int b = threadIdx.x % B;
@@ -254,12 +254,13 @@ __device__ __forceinline__ void strided_body(const cx<T> *__restrict__ in, cx<T>
   });
 }
 
-template <typename T, bool INV, bool PR, class PC>
-__global__ void __launch_bounds__((threads_strided<T, PC>()))
+template <typename T, bool INV, bool PR, class PC, int ROW>
+__global__ void __launch_bounds__((threads_strided<T, PC, ROW>()))
     k_fft_strided(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, int n_in, int n_out,
                   int64_t inner, int ntile, LineMap imap, LineMap omap,
                   const cx<T> *__restrict__ tw, int) {
-  strided_body<T, INV, PR, PC>(in, out, n_in, n_out, inner, ntile, imap, omap, tw, blockIdx.x);
+  strided_body<T, INV, PR, PC, ROW>(in, out, n_in, n_out, inner, ntile, imap, omap, tw,
+                                    blockIdx.x);
 }
 
 // x pass: forward transform along x, spectrum multiply and inverse transform
@@ -311,11 +312,11 @@ constexpr int mid_min_waves() {
 // three-stage plans the twiddle table of exp(-2 pi i e / P): row tables of
 // long lines would cost about as much LDS as the lines themselves (measured on
 // the 2592-point plan: 1.66 ms with row tables, 1.17 ms without)
-template <typename T, class PC>
+template <typename T, class PC, int ROW = 128>
 struct MidLds {
   static constexpr int P = PC::P, ns = PC::ns, R0 = PC::r(0), RM = PC::r(ns - 1);
   static constexpr bool rows = ns == 2;
-  static constexpr int data = ns > 1 ? P * tile_mid<T, PC>() : 0;
+  static constexpr int data = ns > 1 ? P * tile_mid<T, PC, ROW>() : 0;
   static constexpr int flat = ns > 2 ? P : 0;
   static constexpr int mid_rows = rows ? (P / RM) * (RM - 1) : 0;
   static constexpr bool same_rows = (R0 == RM);  // square two-stage plans share one table
@@ -324,18 +325,18 @@ struct MidLds {
 };
 
 // One work-group of the x pass: vb is the launch's block number (XCD vb % 8).
-template <typename T, class PC, bool KYL>
+template <typename T, class PC, bool KYL, int ROW = 128>
 __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int nfield, int Py,
                                          int Pz, int ntile, int slots, int Hy, int Hz,
                                          const cx<T> *__restrict__ ghat,
                                          const cx<T> *__restrict__ tw, int blk, int64_t fstride,
                                          int64_t vb) {
   using V = cx<T>;
-  using ML = MidLds<T, PC>;
+  using ML = MidLds<T, PC, ROW>;
   extern __shared__ unsigned char smem_raw[];
   V *lds = reinterpret_cast<V *>(smem_raw);
   constexpr int P = PC::P, ns = PC::ns;
-  constexpr int B = tile_mid<T, PC>();
+  constexpr int B = tile_mid<T, PC, ROW>();
   constexpr uint32_t SV = sizeof(V);
   // a line holds at most P/2 sources (n_x <= P/2 for even P, checked by the
   // launcher) and only its first P/2 outputs are kept: with an even first
@@ -535,13 +536,13 @@ __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int 
   }
 }
 
-template <typename T, class PC, bool KYL>
-__global__ void __launch_bounds__((threads_mid<T, PC>()), (mid_min_waves<T>()))
+template <typename T, class PC, bool KYL, int ROW>
+__global__ void __launch_bounds__((threads_mid<T, PC, ROW>()), (mid_min_waves<T>()))
     k_fft_mid(cx<T> *__restrict__ data, int n_x, int nfield, int Py, int Pz, int ntile, int slots,
               int Hy, int Hz, const cx<T> *__restrict__ ghat, const cx<T> *__restrict__ tw, int blk,
               int64_t fstride) {
-  mid_body<T, PC, KYL>(data, n_x, nfield, Py, Pz, ntile, slots, Hy, Hz, ghat, tw, blk, fstride,
-                       blockIdx.x);
+  mid_body<T, PC, KYL, ROW>(data, n_x, nfield, Py, Pz, ntile, slots, Hy, Hz, ghat, tw, blk,
+                            fstride, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -620,12 +621,12 @@ void launch_contig(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t lin
   LAUNCHCHECK();
 }
 
-template <typename T, class PC>
-void launch_strided(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t outer, int64_t inner,
-                    const LineMap &imap, const LineMap &omap, bool inverse, const cx<T> *tw,
-                    hipStream_t s) {
-  constexpr int B = tile_strided<T, PC>();
-  constexpr int threads = threads_strided<T, PC>();
+template <typename T, class PC, int ROW>
+void launch_strided_rows(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t outer,
+                         int64_t inner, const LineMap &imap, const LineMap &omap, bool inverse,
+                         const cx<T> *tw, hipStream_t s) {
+  constexpr int B = tile_strided<T, PC, ROW>();
+  constexpr int threads = threads_strided<T, PC, ROW>();
   const int ntile = (int)((inner + B - 1) / B);
   const size_t lds = PC::ns > 1 ? (size_t)PC::P * (B + 1) * sizeof(cx<T>) : 0;
   const int64_t blocks = outer * ntile;
@@ -635,20 +636,28 @@ void launch_strided(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t ou
                        inner, ntile, imap, omap, tw, B);
   };
   if (inverse)
-    pr ? go(k_fft_strided<T, true, true, PC>) : go(k_fft_strided<T, true, false, PC>);
+    pr ? go(k_fft_strided<T, true, true, PC, ROW>) : go(k_fft_strided<T, true, false, PC, ROW>);
   else
-    pr ? go(k_fft_strided<T, false, true, PC>) : go(k_fft_strided<T, false, false, PC>);
+    pr ? go(k_fft_strided<T, false, true, PC, ROW>) : go(k_fft_strided<T, false, false, PC, ROW>);
   LAUNCHCHECK();
 }
 
-// blk > 0: kz-blocked layout [nfield][ceil(Pz/blk)][n_x][Py][blk], tiles of
-// consecutive kz; blk == 0: thin layout [nfield][Pz][n_x][Py] (few kz, as
-// for a flat scatterer), tiles of consecutive ky
+// row_bytes: 128 or 64 (the tile of consecutive lines per work-group)
 template <typename T, class PC>
-void launch_mid(cx<T> *data, int n_x, int nfield, int Py, int Pz, int Hy, int Hz,
-                const cx<T> *ghat, const cx<T> *tw, int blk, int64_t fstride, hipStream_t s) {
-  constexpr int B = tile_mid<T, PC>();
-  constexpr int threads = threads_mid<T, PC>();
+void launch_strided(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t outer, int64_t inner,
+                    const LineMap &imap, const LineMap &omap, bool inverse, const cx<T> *tw,
+                    int row_bytes, hipStream_t s) {
+  if (row_bytes == 64)
+    launch_strided_rows<T, PC, 64>(in, out, n_in, n_out, outer, inner, imap, omap, inverse, tw, s);
+  else
+    launch_strided_rows<T, PC, 128>(in, out, n_in, n_out, outer, inner, imap, omap, inverse, tw, s);
+}
+
+template <typename T, class PC, int ROW>
+void launch_mid_rows(cx<T> *data, int n_x, int nfield, int Py, int Pz, int Hy, int Hz,
+                     const cx<T> *ghat, const cx<T> *tw, int blk, int64_t fstride, hipStream_t s) {
+  constexpr int B = tile_mid<T, PC, ROW>();
+  constexpr int threads = threads_mid<T, PC, ROW>();
   const bool kyl = blk == 0;
   if (PC::r(0) % 2 == 0 && 2 * n_x > PC::P)  // the half-pruned first/last stages need it
     throw Error(AIM_ERR_ARG, "x pass: more than P/2 sources on a line");
@@ -660,21 +669,34 @@ void launch_mid(cx<T> *data, int n_x, int nfield, int Py, int Pz, int Hy, int Hz
     throw Error(AIM_ERR_ARG, "x pass: grid too large for 32-bit offsets");
   const int Pt = kyl ? Py : Pz, Pf = kyl ? Pz : Py;  // tile axis, fixed axis
   const int ntile = (Pt + B - 1) / B;
-  const size_t lds = (size_t)MidLds<T, PC>::total * sizeof(cx<T>);
+  const size_t lds = (size_t)MidLds<T, PC, ROW>::total * sizeof(cx<T>);
   // work items (folded fixed index 0 .. Pf/2, tile, mirror, field), dealt to
   // the XCDs in 8 contiguous ranges
   const int64_t items = 2 * ((int64_t)Pf / 2 + 1) * ntile * nfield;
   const int64_t slots = (items + kXcd - 1) / kXcd;
   if (slots * kXcd > INT32_MAX) throw Error(AIM_ERR_ARG, "x pass: too many tiles");
   if (kyl)
-    hipLaunchKernelGGL((k_fft_mid<T, PC, true>), dim3((unsigned)(slots * kXcd)), dim3(threads),
-                       lds, s, data, n_x, nfield, Py, Pz, ntile, (int)slots, Hy, Hz, ghat, tw, blk,
-                       fstride);
+    hipLaunchKernelGGL((k_fft_mid<T, PC, true, ROW>), dim3((unsigned)(slots * kXcd)),
+                       dim3(threads), lds, s, data, n_x, nfield, Py, Pz, ntile, (int)slots, Hy, Hz,
+                       ghat, tw, blk, fstride);
   else
-    hipLaunchKernelGGL((k_fft_mid<T, PC, false>), dim3((unsigned)(slots * kXcd)), dim3(threads),
-                       lds, s, data, n_x, nfield, Py, Pz, ntile, (int)slots, Hy, Hz, ghat, tw, blk,
-                       fstride);
+    hipLaunchKernelGGL((k_fft_mid<T, PC, false, ROW>), dim3((unsigned)(slots * kXcd)),
+                       dim3(threads), lds, s, data, n_x, nfield, Py, Pz, ntile, (int)slots, Hy, Hz,
+                       ghat, tw, blk, fstride);
   LAUNCHCHECK();
+}
+
+// blk > 0: kz-blocked layout [nfield][ceil(Pz/blk)][n_x][Py][blk], tiles of
+// consecutive kz; blk == 0: thin layout [nfield][Pz][n_x][Py] (few kz, as
+// for a flat scatterer), tiles of consecutive ky. row_bytes: 128 or 64.
+template <typename T, class PC>
+void launch_mid(cx<T> *data, int n_x, int nfield, int Py, int Pz, int Hy, int Hz,
+                const cx<T> *ghat, const cx<T> *tw, int blk, int64_t fstride, int row_bytes,
+                hipStream_t s) {
+  if (row_bytes == 64)
+    launch_mid_rows<T, PC, 64>(data, n_x, nfield, Py, Pz, Hy, Hz, ghat, tw, blk, fstride, s);
+  else
+    launch_mid_rows<T, PC, 128>(data, n_x, nfield, Py, Pz, Hy, Hz, ghat, tw, blk, fstride, s);
 }
 
 // The pipelined y, x and y passes of the kz-blocked layout (see k_fft_xy):

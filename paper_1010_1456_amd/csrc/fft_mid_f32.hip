@@ -4,14 +4,14 @@
 namespace aim {
 void fft_mid_pass(float2 *data, const FftPlan &pl, int n_x, int nfield, int Py, int Pz, int Hx,
                   int Hy, int Hz, const float2 *ghat, const float2 *tw, int blk, int64_t fstride,
-                  hipStream_t s) {
+                  int row_bytes, hipStream_t s) {
   (void)Hx;
   if (nfield <= 0) return;
   switch (pl.P) {
 #define AIM_X(P, a, b, c)                                                                   \
   case P:                                                                                   \
     fftk::launch_mid<float, fftk::PlanC<a, b, c>>(data, n_x, nfield, Py, Pz, Hy, Hz, ghat, tw, \
-                                                blk, fstride, s);                           \
+                                                blk, fstride, row_bytes, s);                           \
     return;
     AIM_FOR_EACH_FFT_PLAN(AIM_X)
 #undef AIM_X

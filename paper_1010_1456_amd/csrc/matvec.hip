@@ -461,7 +461,7 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     view(3, g2, Nx, Py, V2, Py, 1);
     if (stop <= 3) return;
     fft_mid_pass(g2, md.plan[0], Nx, (int)F, Py, 1, md.H[0], md.H[1], 1, ghat2d_of<T>(md),
-                 tw_of<T>(md, 0), 0, V2, s);
+                 tw_of<T>(md, 0), 0, V2, md.x_row[prec], s);
     mark(4);
     view(4, g2, Nx, Py, V2, Py, 1);
     if (stop <= 4) return;
@@ -504,7 +504,7 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     view(3, g2, (int64_t)Nx * Py, Pz, V2, 1, (int64_t)Nx * Py);
     if (stop <= 3) return;
     fft_mid_pass(g2, md.plan[0], Nx, (int)F, Py, Pz, md.H[0], md.H[1], md.H[2], ghat_of<T>(md),
-                 tw_of<T>(md, 0), 0, V2, s);
+                 tw_of<T>(md, 0), 0, V2, md.x_row[prec], s);
     mark(4);
     view(4, g2, (int64_t)Nx * Py, Pz, V2, 1, (int64_t)Nx * Py);
     if (stop <= 4) return;
@@ -604,16 +604,18 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
     blocked_view(4);
     mark(5);
   } else {
-    fft_pass_strided(gz, g2, md.plan[1], Ny, Py, F * Nx, Pz, m1y, m2, false, tw_of<T>(md, 1), s);
+    fft_pass_strided(gz, g2, md.plan[1], Ny, Py, F * Nx, Pz, m1y, m2, false, tw_of<T>(md, 1),
+                     md.y_row[prec], s);
     mark(3);
     blocked_view(3);
     if (stop <= 3) return;
     fft_mid_pass(g2, md.plan[0], Nx, (int)F, Py, Pz, md.H[0], md.H[1], md.H[2], ghat_of<T>(md),
-                 tw_of<T>(md, 0), blk, V2, s);
+                 tw_of<T>(md, 0), blk, V2, md.x_row[prec], s);
     mark(4);
     blocked_view(4);
     if (stop <= 4) return;
-    fft_pass_strided(g2, g1, md.plan[1], Py, Ny, F * Nx, Pz, m2, m1y, true, tw_of<T>(md, 1), s);
+    fft_pass_strided(g2, g1, md.plan[1], Py, Ny, F * Nx, Pz, m2, m1y, true, tw_of<T>(md, 1),
+                     md.y_row[prec], s);
     mark(5);
   }
   view(5, g1, (int64_t)Nx * Ny, Pz, (int64_t)Nx * Ny * Pzs, Pzs, 1);
@@ -873,6 +875,36 @@ void autotune_mesh(Plan *pl, MeshDev &md, hipStream_t s) {
       }
       md.fuse_proj[prec] = choice;
     }
+    // tile rows of the x pass and of the strided y passes (the whole far part
+    // timed; 64-byte rows halve a work-group's LDS tile, so more work-groups
+    // fit a CU, at the cost of half-cache-line accesses)
+    for (int prec = 0; prec < 2; ++prec) {
+      if (prec == 1 && !pl->mixed) break;
+      const int forced = (pl->params.tuning >> 8) & 0xff;
+      md.x_row[prec] = md.y_row[prec] = 128;
+      if (forced == 1 || forced == 2) {  // 1: 128-byte rows, 2: 64-byte rows everywhere
+        md.x_row[prec] = md.y_row[prec] = forced == 2 ? 64 : 128;
+        continue;
+      }
+      // (a variant must beat 128-byte rows by 3%: one-RHS timing spread)
+      float best = 0, base = 0;
+      int bx = 128, by = 128;
+      for (int xr : {128, 64})
+        for (int yr : {128, 64}) {
+          md.x_row[prec] = xr;
+          md.y_row[prec] = yr;
+          const float ms = time_stages(prec, 6);
+          if (xr == 128 && yr == 128) {
+            best = base = ms;
+          } else if (ms < best && ms < 0.97f * base) {
+            best = ms;
+            bx = xr;
+            by = yr;
+          }
+        }
+      md.x_row[prec] = bx;
+      md.y_row[prec] = by;
+    }
     // field groups of the pipelined y / x / y passes (kz-blocked grids with
     // equal x and y lengths)
     for (int prec = 0; prec < 2; ++prec) {
@@ -880,7 +912,7 @@ void autotune_mesh(Plan *pl, MeshDev &md, hipStream_t s) {
       md.xy_groups[prec] = 1;
       const bool thin = prec == 0 ? thin_layout<double>(md.hp.pad[2]) : thin_layout<float>(md.hp.pad[2]);
       if (thin || md.planar_z >= 0 || !xy_pipeline_available(md.plan[0], md.plan[1])) continue;
-      const int forced = pl->params.xy_groups;
+      const int forced = pl->params.tuning & 0xff;
       if (forced > 0) {
         md.xy_groups[prec] = forced;
         continue;

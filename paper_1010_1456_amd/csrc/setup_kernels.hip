@@ -651,8 +651,9 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
                     fftk::contig_map(Pz), false, md.tw64[2], s);
     const fftk::LineMap my = fftk::plain_map((int64_t)Py * Pz, Pz);
     const fftk::LineMap mx = fftk::plain_map(0, (int64_t)Py * Pz);
-    fft_pass_strided(e1, e0, md.plan[1], Py, Py, Px, Pz, my, my, false, md.tw64[1], s);
-    fft_pass_strided(e0, e1, md.plan[0], Px, Px, 1, (int64_t)Py * Pz, mx, mx, false, md.tw64[0], s);
+    fft_pass_strided(e1, e0, md.plan[1], Py, Py, Px, Pz, my, my, false, md.tw64[1], 128, s);
+    fft_pass_strided(e0, e1, md.plan[0], Px, Px, 1, (int64_t)Py * Pz, mx, mx, false, md.tw64[0],
+                     128, s);
     const int64_t noct = (int64_t)md.H[0] * md.H[1] * md.H[2];
     md.ghat64 = (double2 *)dev_alloc(pl, sizeof(double2) * noct);
     hipLaunchKernelGGL(k_extract_octant, dim3(blocks_for(noct, 256)), dim3(256), 0, s, e1,

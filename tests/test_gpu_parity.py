@@ -530,3 +530,51 @@ def test_pipeline_group_count_is_validated():
     m = plate_mesh(1.0, 0.3e9)
     with pytest.raises(A.AimError):
         A.Plan([(m.verts, m.tris, m.freq_hz)], xy_groups=3)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_64_byte_tile_rows(name):
+    """The x and strided y passes with 64-byte tile rows (half the lines per
+    work-group): products against the oracle and every pass against numpy
+    FFTs of the oracle's projected grids (3-D, thin and in-plane layouts)."""
+    from paper_1010_1456_amd import aim as A
+
+    c = case(name)
+    plan = A.Plan([(c.mesh.verts, c.mesh.tris, c.mesh.freq_hz)], order=c.order, tile_rows=64)
+    assert plan.info()["tile_bytes"][0] == ((64, 64), (64, 64))
+    for nrhs, seed in ((1, 111), (3, 112)):
+        x = random_current(c.rwg.n, nrhs=nrhs, seed=seed)
+        ref = oaim.matvec_fft(c.op, x)
+        xt = torch.from_numpy(x).cuda()
+        y = plan.matvec(xt, A.AIM_FP64).cpu().numpy()
+        x32 = x.astype(np.complex64)
+        ref32 = oaim.matvec_fft(c.op, x32.astype(np.complex128))
+        y32 = plan.matvec(torch.from_numpy(x32).cuda(), A.AIM_MIXED).cpu().numpy()
+        for r in range(nrhs):
+            assert rel_max(y[r], ref[r]) <= 1e-10, (nrhs, r)
+            assert rel_max(y32[r], ref32[r]) <= 2e-5, (nrhs, r)
+    x = random_current(c.rwg.n, nrhs=2, seed=113)
+    xt = torch.from_numpy(x).cuda()
+    refs = _reference_stages(c, x)
+    for P, tol in ((A.AIM_FP64, 1e-12), (A.AIM_MIXED, 3e-6)):
+        for stage in range(1, 7):
+            got = plan.far_stage(0, xt, stage, P).cpu().numpy()
+            assert np.abs(got - refs[stage]).max() <= tol * np.abs(refs[stage]).max(), (P, stage)
+    plan.close()
+
+
+def test_tuning_values_are_validated():
+    from paper_1010_1456_amd import aim as A
+
+    m = plate_mesh(1.0, 0.3e9)
+    p = A._params(0.1, 2, 0.3)
+    p.tuning = 3 << 8
+    L = A.lib()
+    keep = []
+    arr = (A.AimMesh * 1)()
+    arr[0] = A._mesh_struct(m.verts, m.tris, m.freq_hz, keep)
+    import ctypes
+
+    h = ctypes.c_void_p()
+    assert L.aim_setup(arr, 1, ctypes.byref(p), None, None, ctypes.byref(h)) == A.AIM_ERR_ARG
+    assert h.value is None
