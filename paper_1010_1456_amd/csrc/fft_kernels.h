@@ -32,6 +32,11 @@ namespace fftk {
 using namespace fftc;
 
 constexpr int kLdsBudget = 48 * 1024;
+// Work-groups of a launch are dealt round-robin to the 8 XCDs, each with its
+// own L2; kernels that number their work in contiguous ranges per XCD
+// (block b does item (b % kXcd) * slots + b / kXcd) keep neighbouring items,
+// e.g. the fields of one grid line, in one L2.
+constexpr int kXcd = 8;
 
 
 template <int R0, int R1, int R2>
@@ -121,12 +126,18 @@ template <typename T, bool INV, bool PR, class PC>
 __global__ void __launch_bounds__((threads_contig<T, PC>()))
     k_fft_contig(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, int n_in, int n_out,
                  int64_t lines, ContigMap imap, ContigMap omap, const cx<T> *__restrict__ tw,
-                 int B) {
+                 int B, int64_t slots) {
   using V = cx<T>;
   extern __shared__ unsigned char smem_raw[];
   V *lds = reinterpret_cast<V *>(smem_raw);
   constexpr int P = PC::P, LS = P + 1;
-  const int64_t line0 = (int64_t)blockIdx.x * B;
+  // slots > 0: tiles in contiguous ranges per XCD, so that the fields of a
+  // line (consecutive pass lines of an interleaved layout) that fall in
+  // different tiles go through one L2; tiles past the last line have no
+  // active thread
+  const int64_t tile =
+      slots ? (int64_t)(blockIdx.x % kXcd) * slots + blockIdx.x / kXcd : (int64_t)blockIdx.x;
+  const int64_t line0 = tile * B;
   V *twl = lds + (PC::ns > 1 ? B * LS : 0);  // twiddle table in LDS
   if constexpr (PC::ns > 1) {
     for (int i = threadIdx.x; i < P; i += blockDim.x) twl[i] = tw[i];
@@ -269,13 +280,12 @@ __global__ void __launch_bounds__((threads_strided<T, PC, ROW>()))
 // kz-blocked layout, or consecutive ky of the thin layout) in one field. The
 // fields of a tile, and the fields of its mirror tile (Py - ky, resp.
 // Pz - kz: the same octant rows), get consecutive numbers, and consecutive
-// numbers go to the same XCD (work-groups are dealt round-robin to the 8
-// XCDs), so the octant rows a tile reads are mostly found in that XCD's L2.
+// numbers go to the same XCD, so the octant rows a tile reads are mostly
+// found in that XCD's L2.
 // Global accesses are buffer loads and stores: a work-group-uniform resource
 // and scalar offset plus a per-thread 32-bit offset fixed for the whole kernel
 // (the launcher checks the ranges), which keeps address arithmetic off the
 // vector ALU.
-constexpr int kXcd = 8;
 constexpr int kBufferWord3 = 0x00020000;  // raw buffer resource, 32-bit data format
 
 using u32x2 = unsigned int __attribute__((ext_vector_type(2)));
@@ -609,10 +619,18 @@ void launch_contig(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t lin
   constexpr int threads = threads_contig<T, PC>();
   const size_t lds = PC::ns > 1 ? ((size_t)B * (PC::P + 1) + PC::P) * sizeof(cx<T>) : 0;
   const int64_t blocks = (lines + B - 1) / B;
+  // a tile narrower than the fields of a line: ranges per XCD (measured on the
+  // in-plane inverse y pass, whose field-interleaved stores otherwise leave
+  // partly written lines in four L2s: 128-lambda plate 71 -> 54 us); wider
+  // tiles keep the plain numbering
+  const int64_t slots =
+      (B < std::max(imap.fin, omap.fin)) ? (blocks + kXcd - 1) / kXcd : 0;
+  const int64_t launched = slots ? slots * kXcd : blocks;
+  if (launched > INT32_MAX) throw Error(AIM_ERR_ARG, "contiguous pass: too many lines");
   const bool pr = pass_prunable<PC>(inverse, n_in, n_out);
   auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), lds, s, in, out, n_in, n_out,
-                       lines, imap, omap, tw, B);
+    hipLaunchKernelGGL(kern, dim3((unsigned)launched), dim3(threads), lds, s, in, out, n_in,
+                       n_out, lines, imap, omap, tw, B, slots);
   };
   if (inverse)
     pr ? go(k_fft_contig<T, true, true, PC>) : go(k_fft_contig<T, true, false, PC>);
