@@ -269,9 +269,16 @@ template <typename T, bool INV, bool PR, class PC, int ROW>
 __global__ void __launch_bounds__((threads_strided<T, PC, ROW>()))
     k_fft_strided(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, int n_in, int n_out,
                   int64_t inner, int ntile, LineMap imap, LineMap omap,
-                  const cx<T> *__restrict__ tw, int) {
-  strided_body<T, INV, PR, PC, ROW>(in, out, n_in, n_out, inner, ntile, imap, omap, tw,
-                                    blockIdx.x);
+                  const cx<T> *__restrict__ tw, int64_t tiles, int64_t slots) {
+  int64_t vb = blockIdx.x;
+  if constexpr (ROW < 128) {
+    // two tiles share each 128-byte line: adjacent tiles go to one XCD (its
+    // tiles in one contiguous range, taken in order), so the second read of a
+    // line, and the second half of a line's writes, meet the first in its L2
+    vb = (int64_t)(blockIdx.x % kXcd) * slots + blockIdx.x / kXcd;
+    if (vb >= tiles) return;  // the whole work-group
+  }
+  strided_body<T, INV, PR, PC, ROW>(in, out, n_in, n_out, inner, ntile, imap, omap, tw, vb);
 }
 
 // x pass: forward transform along x, spectrum multiply and inverse transform
@@ -648,10 +655,13 @@ void launch_strided_rows(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64
   const int ntile = (int)((inner + B - 1) / B);
   const size_t lds = PC::ns > 1 ? (size_t)PC::P * (B + 1) * sizeof(cx<T>) : 0;
   const int64_t blocks = outer * ntile;
+  const int64_t slots = ROW < 128 ? (blocks + kXcd - 1) / kXcd : 0;
+  const int64_t launched = ROW < 128 ? slots * kXcd : blocks;
+  if (launched > INT32_MAX) throw Error(AIM_ERR_ARG, "strided pass: too many tiles");
   const bool pr = pass_prunable<PC>(inverse, n_in, n_out);
   auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), lds, s, in, out, n_in, n_out,
-                       inner, ntile, imap, omap, tw, B);
+    hipLaunchKernelGGL(kern, dim3((unsigned)launched), dim3(threads), lds, s, in, out, n_in,
+                       n_out, inner, ntile, imap, omap, tw, blocks, slots);
   };
   if (inverse)
     pr ? go(k_fft_strided<T, true, true, PC, ROW>) : go(k_fft_strided<T, true, false, PC, ROW>);
