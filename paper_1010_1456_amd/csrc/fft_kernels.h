@@ -319,27 +319,51 @@ __device__ __forceinline__ void bstore(V v, __amdgpu_buffer_rsrc_t r, uint32_t v
                                            0);
 }
 
-// waves per SIMD the x pass must fit in registers (its LDS allows about 4)
+// waves per SIMD the x pass aims to fit in registers where LDS allows them
 template <typename T>
-constexpr int mid_min_waves() {
-  return sizeof(T) == 4 ? 4 : 3;
+constexpr int mid_target_waves() {
+  return sizeof(T) == 4 ? 7 : 3;
 }
 // LDS of the x pass: the tile's lines, and for two-stage plans the row tables
 // of the middle stage and of the inverse's last stage (about P entries), for
 // three-stage plans the twiddle table of exp(-2 pi i e / P): row tables of
 // long lines would cost about as much LDS as the lines themselves (measured on
 // the 2592-point plan: 1.66 ms with row tables, 1.17 ms without)
+// Where the tile's lines would limit the work-groups per CU below what the
+// registers allow, two-stage plans exchange each line through LDS in two
+// halves (the first ceil(R/2) outputs of every butterfly, then the rest), so
+// the line buffer holds about half a tile (8-lambda sphere, 324-point lines:
+// 3 -> 5 work-groups per CU for c64, 0.357 -> 0.352 ms; 3 -> 6 for c128,
+// 0.676 -> 0.629 ms). Shorter lines keep the one-step exchange: their tiles
+// do not limit the occupancy, and the extra barriers cost time.
 template <typename T, class PC, int ROW = 128>
 struct MidLds {
   static constexpr int P = PC::P, ns = PC::ns, R0 = PC::r(0), RM = PC::r(ns - 1);
   static constexpr bool rows = ns == 2;
-  static constexpr int data = ns > 1 ? P * tile_mid<T, PC, ROW>() : 0;
   static constexpr int flat = ns > 2 ? P : 0;
   static constexpr int mid_rows = rows ? (P / RM) * (RM - 1) : 0;
   static constexpr bool same_rows = (R0 == RM);  // square two-stage plans share one table
   static constexpr int last_rows = (rows && !same_rows) ? (P / R0) * (R0 - 1) : 0;
+  static constexpr int S0 = (R0 + 1) / 2, S1 = (RM + 1) / 2;  // first-half output counts
+  static constexpr int half = (S0 * RM > S1 * R0 ? S0 * RM : S1 * R0);
+  static constexpr int B = tile_mid<T, PC, ROW>();
+  static constexpr long tables = (long)(flat + mid_rows + last_rows) * (long)sizeof(cx<T>);
+  static constexpr long lds_cu = 160 * 1024;
+  static constexpr int groups_by_waves =
+      4 * mid_target_waves<T>() / ((threads_mid<T, PC, ROW>() + 63) / 64);
+  static constexpr bool split =
+      ns == 2 && lds_cu / ((long)P * B * (long)sizeof(cx<T>) + tables) < groups_by_waves;
+  static constexpr int data = ns > 1 ? (split ? half : P) * B : 0;
   static constexpr int total = data + flat + mid_rows + last_rows;
 };
+// waves per SIMD the x pass must fit in registers: the target where the split
+// exchange or a three-stage plan leaves LDS for them (128-lambda plate,
+// 2592-point lines: 0.173 -> 0.165 ms for c64), else 4 for c64 (shorter
+// lines measured slower when squeezed to 72 registers)
+template <typename T, class PC, int ROW = 128>
+constexpr int mid_min_waves() {
+  return (sizeof(T) == 8 || MidLds<T, PC, ROW>::split || PC::ns > 2) ? mid_target_waves<T>() : 4;
+}
 
 // One work-group of the x pass: vb is the launch's block number (XCD vb % 8).
 template <typename T, class PC, bool KYL, int ROW = 128>
@@ -469,6 +493,81 @@ __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int 
         if (p < n_x) bstore(v0[p], fr, o_beta, t0 + (uint32_t)(p * es) * SV);
       });
     }
+  } else if constexpr (ML::split) {
+    // forward stage 1 (L = 1: no twiddles) -> LDS -> forward stage 2,
+    // spectrum, inverse stage 1 in registers -> LDS -> inverse stage 2. Each
+    // exchange runs in two halves: butterfly outputs p < S first (read by the
+    // next stage's butterflies j < S), then p >= S (butterflies j >= S).
+    constexpr int S0 = ML::S0, S1 = ML::S1;
+    __syncthreads();  // twiddle tables ready
+    if (act0) {
+      if constexpr (HALF) dft_upper_zero<R0, false, V>(v0);
+      else Dft<R0, false, V>::run(v0);
+    }
+    V v[RM];
+    // stage-1 butterfly beta's output p is element p Mp0 + beta; middle
+    // butterfly j reads elements j RM + q (Mp0 = RM)
+    auto exchange1 = [&](auto half_) AIM_AI {
+      constexpr int h = decltype(half_)::value;
+      constexpr int p0 = h ? S0 : 0, p1 = h ? R0 : S0;
+      if (act0)
+        static_for<p1 - p0>([&](auto p_) AIM_AI {
+          constexpr int p = decltype(p_)::value + p0;
+          lds[((p - p0) * Mp0 + beta) * B + b] = v0[p];
+        });
+      __syncthreads();
+      if (act_mid && (h ? j >= S0 : j < S0))
+        static_for<RM>([&](auto q_) AIM_AI {
+          constexpr int q = decltype(q_)::value;
+          v[q] = lds[((j - p0) * RM + q) * B + b];
+        });
+      __syncthreads();
+    };
+    exchange1(std::integral_constant<int, 0>{});
+    exchange1(std::integral_constant<int, 1>{});
+    if (act_mid) {
+      const V *row = twm + j * (RM - 1);
+      static_for<RM - 1>([&](auto q_) AIM_AI {
+        constexpr int q = decltype(q_)::value + 1;
+        v[q] = tw_mul<false>(v[q], row, q - 1);
+      });
+      Dft<RM, false, V>::run(v);
+      V g[RM];
+      spectrum(g);
+      static_for<RM>([&](auto p_) AIM_AI {
+        constexpr int p = decltype(p_)::value;
+        v[p] = cmul(v[p], g[p]);
+      });
+      Dft<RM, true, V>::run(v);
+    }
+    // middle butterfly j's output p is element p LM + j (LM = R0); the
+    // inverse's last stage (radix R0, L = RM, M' = 1) butterfly beta reads
+    // elements beta R0 + q
+    V w[R0];
+    const bool act_last = line_ok && (beta < RM);
+    auto exchange2 = [&](auto half_) AIM_AI {
+      constexpr int h = decltype(half_)::value;
+      constexpr int p0 = h ? S1 : 0, p1 = h ? RM : S1;
+      if (act_mid)
+        static_for<p1 - p0>([&](auto p_) AIM_AI {
+          constexpr int p = decltype(p_)::value + p0;
+          lds[((p - p0) * LM + j) * B + b] = v[p];
+        });
+      __syncthreads();
+      if (act_last && (h ? beta >= S1 : beta < S1))
+        static_for<R0>([&](auto q_) AIM_AI {
+          constexpr int q = decltype(q_)::value;
+          w[q] = lds[((beta - p0) * R0 + q) * B + b];
+        });
+      if constexpr (h == 0) __syncthreads();
+    };
+    exchange2(std::integral_constant<int, 0>{});
+    exchange2(std::integral_constant<int, 1>{});
+    auto st = [&](int i, V x) AIM_AI {
+      if (i < n_x) bstore(x, fr, o_beta, t0 + (uint32_t)((i - beta) * es) * SV);
+    };
+    if (act_last)
+      stage_compute_store_p<R0, true, false, HALF ? R0 / 2 : R0, true>(w, beta, RM, 1, twr, st);
   } else {
     __syncthreads();  // twiddle tables ready
     // first forward stage
@@ -554,7 +653,7 @@ __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int 
 }
 
 template <typename T, class PC, bool KYL, int ROW>
-__global__ void __launch_bounds__((threads_mid<T, PC, ROW>()), (mid_min_waves<T>()))
+__global__ void __launch_bounds__((threads_mid<T, PC, ROW>()), (mid_min_waves<T, PC, ROW>()))
     k_fft_mid(cx<T> *__restrict__ data, int n_x, int nfield, int Py, int Pz, int ntile, int slots,
               int Hy, int Hz, const cx<T> *__restrict__ ghat, const cx<T> *__restrict__ tw, int blk,
               int64_t fstride) {
@@ -596,7 +695,7 @@ constexpr int threads_xy() {
 }
 
 template <typename T, class PC, bool PRF, bool PRI>
-__global__ void __launch_bounds__((threads_xy<T, PC>()), (mid_min_waves<T>()))
+__global__ void __launch_bounds__((threads_xy<T, PC>()), (sizeof(T) == 4 ? 4 : 3))
     k_fft_xy(XyMid<T> xm, XyStrided<T> yf, XyStrided<T> yi, const cx<T> *__restrict__ ghat,
              const cx<T> *__restrict__ twx, const cx<T> *__restrict__ twy, int64_t nruns,
              int64_t yruns) {
