@@ -87,9 +87,26 @@ template <typename T, class PC, int ROW = 128>
 constexpr int tile_mid() {
   return tile_rows<T, PC>(ROW);
 }
-template <typename T, class PC, int ROW = 128>
+// Wide x-pass work-groups, for two-stage plans whose first radix is twice the
+// middle one (P = 2 R R, e.g. 162 = 18 x 9): the first and last stages have
+// half as many butterflies per line as the middle stage, so with one thread
+// per middle butterfly half the threads idle in those stages. A wide
+// work-group gives each line R threads instead, each thread two middle
+// butterflies, and takes kMidWideRows rows (tiles) of lines, so that the
+// thread count fills whole waves.
+constexpr int kMidWideRows = 4;
+template <class PC>
+constexpr bool mid_wide_plan() {
+  return PC::ns == 2 && PC::r(0) == 2 * PC::r(1);
+}
+// threads per line of an x-pass work-group
+template <class PC, bool WIDE>
+constexpr int mid_tpl() {
+  return WIDE ? PC::P / PC::r(0) : PC::maxnb();
+}
+template <typename T, class PC, int ROW = 128, bool WIDE = false>
 constexpr int threads_mid() {
-  return round_up_c(PC::maxnb() * tile_mid<T, PC, ROW>(), 64);
+  return round_up_c(mid_tpl<PC, WIDE>() * tile_mid<T, PC, ROW>() * (WIDE ? kMidWideRows : 1), 64);
 }
 template <typename T, class PC>
 constexpr int tile_contig() {
@@ -336,7 +353,7 @@ constexpr int mid_target_waves() {
 // 3 -> 5 work-groups per CU for c64, 0.357 -> 0.352 ms; 3 -> 6 for c128,
 // 0.676 -> 0.629 ms). Shorter lines keep the one-step exchange: their tiles
 // do not limit the occupancy, and the extra barriers cost time.
-template <typename T, class PC, int ROW = 128>
+template <typename T, class PC, int ROW = 128, bool WIDE = false>
 struct MidLds {
   static constexpr int P = PC::P, ns = PC::ns, R0 = PC::r(0), RM = PC::r(ns - 1);
   static constexpr bool rows = ns == 2;
@@ -346,13 +363,14 @@ struct MidLds {
   static constexpr int last_rows = (rows && !same_rows) ? (P / R0) * (R0 - 1) : 0;
   static constexpr int S0 = (R0 + 1) / 2, S1 = (RM + 1) / 2;  // first-half output counts
   static constexpr int half = (S0 * RM > S1 * R0 ? S0 * RM : S1 * R0);
-  static constexpr int B = tile_mid<T, PC, ROW>();
+  static constexpr int B = tile_mid<T, PC, ROW>() * (WIDE ? kMidWideRows : 1);  // lines
   static constexpr long tables = (long)(flat + mid_rows + last_rows) * (long)sizeof(cx<T>);
   static constexpr long lds_cu = 160 * 1024;
   static constexpr int groups_by_waves =
-      4 * mid_target_waves<T>() / ((threads_mid<T, PC, ROW>() + 63) / 64);
+      4 * mid_target_waves<T>() / ((threads_mid<T, PC, ROW, WIDE>() + 63) / 64);
   static constexpr bool split =
-      ns == 2 && lds_cu / ((long)P * B * (long)sizeof(cx<T>) + tables) < groups_by_waves;
+      ns == 2 &&
+      (WIDE || lds_cu / ((long)P * B * (long)sizeof(cx<T>) + tables) < groups_by_waves);
   static constexpr int data = ns > 1 ? (split ? half : P) * B : 0;
   static constexpr int total = data + flat + mid_rows + last_rows;
 };
@@ -360,24 +378,26 @@ struct MidLds {
 // exchange or a three-stage plan leaves LDS for them (128-lambda plate,
 // 2592-point lines: 0.173 -> 0.165 ms for c64), else 4 for c64 (shorter
 // lines measured slower when squeezed to 72 registers)
-template <typename T, class PC, int ROW = 128>
+template <typename T, class PC, int ROW = 128, bool WIDE = false>
 constexpr int mid_min_waves() {
-  return (sizeof(T) == 8 || MidLds<T, PC, ROW>::split || PC::ns > 2) ? mid_target_waves<T>() : 4;
+  return (sizeof(T) == 8 || MidLds<T, PC, ROW, WIDE>::split || PC::ns > 2) ? mid_target_waves<T>()
+                                                                           : 4;
 }
 
 // One work-group of the x pass: vb is the launch's block number (XCD vb % 8).
-template <typename T, class PC, bool KYL, int ROW = 128>
+template <typename T, class PC, bool KYL, int ROW = 128, bool WIDE = false>
 __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int nfield, int Py,
                                          int Pz, int ntile, int slots, int Hy, int Hz,
                                          const cx<T> *__restrict__ ghat,
                                          const cx<T> *__restrict__ tw, int blk, int64_t fstride,
                                          int64_t vb) {
   using V = cx<T>;
-  using ML = MidLds<T, PC, ROW>;
+  using ML = MidLds<T, PC, ROW, WIDE>;
   extern __shared__ unsigned char smem_raw[];
   V *lds = reinterpret_cast<V *>(smem_raw);
   constexpr int P = PC::P, ns = PC::ns;
-  constexpr int B = tile_mid<T, PC, ROW>();
+  constexpr int B = ML::B;  // lines of the work-group (consecutive along the tile axis)
+  static_assert(!WIDE || (mid_wide_plan<PC>() && ML::split), "wide work-groups");
   constexpr uint32_t SV = sizeof(V);
   // a line holds at most P/2 sources (n_x <= P/2 for even P, checked by the
   // launcher) and only its first P/2 outputs are kept: with an even first
@@ -412,15 +432,21 @@ __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int 
   const int fky = KYL ? fl : ff, fkz = KYL ? ff : fl;
   const int gplane = Hy * Hz;
   const int es = KYL ? Py : Py * blk;  // elements between x and x + 1 of a line
-  // field data: resource over one kz block (one kz plane for KYL) of this
-  // field; the tile's first line starts at byte t0 of it, thread (b, beta)
-  // adds o_beta
+  // field data: resource over the kz blocks of the work-group's lines (one kz
+  // plane for KYL) of this field; its first line starts at byte t0, thread
+  // (b, beta) adds o_beta
   const int64_t blk_elems = (int64_t)n_x * es;
-  const __amdgpu_buffer_rsrc_t fr =
-      buffer_of(data + field * fstride + (int64_t)(KYL ? fixed : k0 / blk) * blk_elems,
-                (uint32_t)blk_elems * SV);
-  const uint32_t t0 = (uint32_t)(KYL ? k0 : fixed * blk + k0 % blk) * SV;
-  const uint32_t o_beta = (uint32_t)(b + beta * es) * SV;
+  constexpr int WB = WIDE ? kMidWideRows : 1;  // kz blocks a work-group may span
+  const int kb0 = KYL ? fixed : k0 / blk;
+  const int nres = KYL ? 1 : min(WB, (Pz + blk - 1) / blk - kb0);
+  const __amdgpu_buffer_rsrc_t fr = buffer_of(data + field * fstride + (int64_t)kb0 * blk_elems,
+                                              (uint32_t)(blk_elems * nres) * SV);
+  const int kin = KYL ? 0 : k0 % blk + b;  // the line's kz from its first block
+  const uint32_t t0 = (uint32_t)(KYL ? k0 : fixed * blk) * SV;
+  const uint32_t o_beta =
+      (uint32_t)((KYL || !WIDE) ? (KYL ? b : kin) + beta * es
+                                : (int64_t)(kin / blk) * blk_elems + kin % blk + (int64_t)beta * es) *
+      SV;
 
   // spectrum values of the middle butterfly j = beta (kx = j + LM p): kx <
   // P/2 for 2p <= RM - 2 (row kx), kx >= P/2 for 2p >= RM (row P - kx); only
@@ -428,7 +454,7 @@ __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int 
   // used: issued at entry they delay the first stage's loads.
   const int j = beta;
   const bool act_mid = line_ok && (beta < LM);
-  auto spectrum = [&](V *g) AIM_AI {
+  auto spectrum = [&](V *g, const int j) AIM_AI {
     const int gofs = fky * Hz + fkz;
     const __amdgpu_buffer_rsrc_t gres =
         buffer_of(ghat, (uint32_t)gplane * (uint32_t)(P / 2 + 1) * SV);
@@ -482,7 +508,7 @@ __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int 
       if constexpr (HALF) dft_upper_zero<R0, false, V>(v0);
       else Dft<R0, false, V>::run(v0);
       V g[R0];
-      spectrum(g);
+      spectrum(g, j);
       static_for<R0>([&](auto p_) AIM_AI {
         constexpr int p = decltype(p_)::value;
         v0[p] = cmul(v0[p], g[p]);
@@ -493,6 +519,77 @@ __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int 
         if (p < n_x) bstore(v0[p], fr, o_beta, t0 + (uint32_t)(p * es) * SV);
       });
     }
+  } else if constexpr (WIDE) {
+    // P = R0 RM with R0 = 2 RM: thread beta < RM of a line runs first-stage
+    // butterfly beta, middle butterflies beta and beta + RM, and last-stage
+    // butterfly beta. Exchange 1 in two halves: first-stage outputs p < RM
+    // feed middle butterflies j < RM (each thread's first), p >= RM the others;
+    // exchange 2 by output halves as in the split exchange below.
+    constexpr int S1 = ML::S1;
+    const bool act = line_ok && (beta < RM);  // Mp0 = P / R0 = RM
+    __syncthreads();  // twiddle tables ready
+    if (act) dft_upper_zero<R0, false, V>(v0);
+    V va[RM], vb[RM];
+    static_for<2>([&](auto h_) AIM_AI {
+      constexpr int h = decltype(h_)::value;
+      // stage-1 output p (< R0) of butterfly beta is element p RM + beta;
+      // middle butterfly jj reads elements jj RM + q
+      if (act)
+        static_for<RM>([&](auto p_) AIM_AI {
+          constexpr int p = decltype(p_)::value;
+          lds[(p * RM + beta) * B + b] = v0[p + h * RM];
+        });
+      __syncthreads();
+      if (act)
+        static_for<RM>([&](auto q_) AIM_AI {
+          constexpr int q = decltype(q_)::value;
+          (h ? vb : va)[q] = lds[(beta * RM + q) * B + b];
+        });
+      __syncthreads();
+    });
+    auto middle = [&](V *v, const int jj) AIM_AI {
+      const V *row = twm + jj * (RM - 1);
+      static_for<RM - 1>([&](auto q_) AIM_AI {
+        constexpr int q = decltype(q_)::value + 1;
+        v[q] = tw_mul<false>(v[q], row, q - 1);
+      });
+      Dft<RM, false, V>::run(v);
+      V g[RM];
+      spectrum(g, jj);
+      static_for<RM>([&](auto p_) AIM_AI {
+        constexpr int p = decltype(p_)::value;
+        v[p] = cmul(v[p], g[p]);
+      });
+      Dft<RM, true, V>::run(v);
+    };
+    if (act) {
+      middle(va, beta);
+      middle(vb, beta + RM);
+    }
+    // middle butterfly jj's output p is element p LM + jj (LM = R0); the last
+    // stage's butterfly beta reads elements beta R0 + q
+    V w[R0];
+    static_for<2>([&](auto h_) AIM_AI {
+      constexpr int h = decltype(h_)::value;
+      constexpr int p0 = h ? S1 : 0, p1 = h ? RM : S1;
+      if (act)
+        static_for<p1 - p0>([&](auto p_) AIM_AI {
+          constexpr int p = decltype(p_)::value + p0;
+          lds[((p - p0) * LM + beta) * B + b] = va[p];
+          lds[((p - p0) * LM + beta + RM) * B + b] = vb[p];
+        });
+      __syncthreads();
+      if (act && (h ? beta >= S1 : beta < S1))
+        static_for<R0>([&](auto q_) AIM_AI {
+          constexpr int q = decltype(q_)::value;
+          w[q] = lds[((beta - p0) * R0 + q) * B + b];
+        });
+      if constexpr (h == 0) __syncthreads();
+    });
+    auto st = [&](int i, V x) AIM_AI {
+      if (i < n_x) bstore(x, fr, o_beta, t0 + (uint32_t)((i - beta) * es) * SV);
+    };
+    if (act) stage_compute_store_p<R0, true, false, R0 / 2, true>(w, beta, RM, 1, twr, st);
   } else if constexpr (ML::split) {
     // forward stage 1 (L = 1: no twiddles) -> LDS -> forward stage 2,
     // spectrum, inverse stage 1 in registers -> LDS -> inverse stage 2. Each
@@ -533,7 +630,7 @@ __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int 
       });
       Dft<RM, false, V>::run(v);
       V g[RM];
-      spectrum(g);
+      spectrum(g, j);
       static_for<RM>([&](auto p_) AIM_AI {
         constexpr int p = decltype(p_)::value;
         v[p] = cmul(v[p], g[p]);
@@ -613,7 +710,7 @@ __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int 
         }
         Dft<RM, false, V>::run(v);
         V g[RM];
-        spectrum(g);
+        spectrum(g, j);
         static_for<RM>([&](auto p_) AIM_AI {
           constexpr int p = decltype(p_)::value;
           v[p] = cmul(v[p], g[p]);
@@ -653,12 +750,13 @@ __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int 
 }
 
 template <typename T, class PC, bool KYL, int ROW>
-__global__ void __launch_bounds__((threads_mid<T, PC, ROW>()), (mid_min_waves<T, PC, ROW>()))
+__global__ void __launch_bounds__((threads_mid<T, PC, ROW, mid_wide_plan<PC>()>()),
+                                  (mid_min_waves<T, PC, ROW, mid_wide_plan<PC>()>()))
     k_fft_mid(cx<T> *__restrict__ data, int n_x, int nfield, int Py, int Pz, int ntile, int slots,
               int Hy, int Hz, const cx<T> *__restrict__ ghat, const cx<T> *__restrict__ tw, int blk,
               int64_t fstride) {
-  mid_body<T, PC, KYL, ROW>(data, n_x, nfield, Py, Pz, ntile, slots, Hy, Hz, ghat, tw, blk,
-                            fstride, blockIdx.x);
+  mid_body<T, PC, KYL, ROW, mid_wide_plan<PC>()>(data, n_x, nfield, Py, Pz, ntile, slots, Hy, Hz,
+                                                 ghat, tw, blk, fstride, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -783,20 +881,23 @@ void launch_strided(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t ou
 template <typename T, class PC, int ROW>
 void launch_mid_rows(cx<T> *data, int n_x, int nfield, int Py, int Pz, int Hy, int Hz,
                      const cx<T> *ghat, const cx<T> *tw, int blk, int64_t fstride, hipStream_t s) {
-  constexpr int B = tile_mid<T, PC, ROW>();
-  constexpr int threads = threads_mid<T, PC, ROW>();
+  constexpr bool WIDE = mid_wide_plan<PC>();
+  constexpr int B = MidLds<T, PC, ROW, WIDE>::B;  // lines per work-group
+  constexpr int threads = threads_mid<T, PC, ROW, WIDE>();
   const bool kyl = blk == 0;
   if (PC::r(0) % 2 == 0 && 2 * n_x > PC::P)  // the half-pruned first/last stages need it
     throw Error(AIM_ERR_ARG, "x pass: more than P/2 sources on a line");
-  if (blk < 0 || (!kyl && blk % B != 0))
-    throw Error(AIM_ERR_ARG, "x pass: tile does not divide the kz block");
-  // 32-bit buffer offsets: one kz block (kz plane) of a field, and the octant
-  if ((uint64_t)n_x * Py * (kyl ? 1 : blk) * sizeof(cx<T>) >= (1ull << 31) ||
+  if (blk < 0 || (!kyl && (B <= blk ? blk % B : B % blk) != 0))
+    throw Error(AIM_ERR_ARG, "x pass: work-group lines and kz blocks do not tile");
+  // 32-bit buffer offsets: the kz blocks of a work-group (a kz plane) of a
+  // field, and the octant
+  const uint64_t wblocks = (!kyl && B > blk) ? (uint64_t)(B / blk) : 1;
+  if ((uint64_t)n_x * Py * (kyl ? 1 : blk) * wblocks * sizeof(cx<T>) >= (1ull << 31) ||
       (uint64_t)Hy * Hz * (PC::P / 2 + 1) * sizeof(cx<T>) >= (1ull << 31))
     throw Error(AIM_ERR_ARG, "x pass: grid too large for 32-bit offsets");
   const int Pt = kyl ? Py : Pz, Pf = kyl ? Pz : Py;  // tile axis, fixed axis
   const int ntile = (Pt + B - 1) / B;
-  const size_t lds = (size_t)MidLds<T, PC, ROW>::total * sizeof(cx<T>);
+  const size_t lds = (size_t)MidLds<T, PC, ROW, WIDE>::total * sizeof(cx<T>);
   // work items (folded fixed index 0 .. Pf/2, tile, mirror, field), dealt to
   // the XCDs in 8 contiguous ranges
   const int64_t items = 2 * ((int64_t)Pf / 2 + 1) * ntile * nfield;
