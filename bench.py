@@ -182,6 +182,27 @@ def stage_bytes(info, mesh, nrhs, s_grid, s_real, s_x, s_y, path):
     ], dtype=np.float64)
 
 
+def x_pass_flops(info, nrhs):
+    """Algorithmic floating-point operations of the x pass of one product,
+    summed over the scatterers: per line a forward and an inverse complex FFT
+    of the padded length P (5 P log2 P each, the radix-2 count) and the
+    spectrum multiply (6 P); lines = fields x P_y x P_z (P_y only for a
+    scatterer in one grid plane)."""
+    total = 0.0
+    for mesh in range(info["nmesh"]):
+        Px, Py, Pz = info["pad"][mesh]
+        lines = 4 * nrhs * Py * (1 if info["planar_z"][mesh] >= 0 else Pz)
+        total += lines * (2 * 5 * Px * np.log2(Px) + 6 * Px)
+    return total
+
+
+# FP32 vector peak of the chip's units without packed-FP32 instructions (the
+# build disables them): 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz;
+# the vendor's 157.3 TFLOP/s counts packed FP32
+FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+FP32_VECTOR_TFLOPS = 157.3
+
+
 def pipelined_bytes(info, mesh, path, b):
     """With the y, x and y passes pipelined in one kernel (aim_info.xy_groups
     > 1) their stage boundaries fall together and the forward y step carries
@@ -191,6 +212,18 @@ def pipelined_bytes(info, mesh, path, b):
         b[2] += b[3] + b[4]
         b[3] = b[4] = 0.0
     return b
+
+
+def x_pass_alu(info, nrhs, ms):
+    """The x pass is bound by vector-ALU issue rather than HBM: its FLOP rate
+    against the FP32 vector peaks."""
+    fl = x_pass_flops(info, nrhs)
+    tf = fl / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "flops_per_launch": fl, "avg_launch_ms": float(ms),
+            "achieved_TFLOPs": tf,
+            "peak_TFLOPs_nonpacked": FP32_NONPACKED_TFLOPS, "frac_nonpacked": tf / FP32_NONPACKED_TFLOPS,
+            "peak_TFLOPs_vector": FP32_VECTOR_TFLOPS, "frac_vector": tf / FP32_VECTOR_TFLOPS,
+            "convention": "2 x 5 P log2 P + 6 P per line (forward and inverse FFT, spectrum multiply)"}
 
 
 def fill_report(info):
@@ -691,6 +724,7 @@ def main(argv=None):
             "copy_GBs": copy_gbs,
             "frac_of_copy": achieved / copy_gbs,
         },
+        "x_pass_alu": x_pass_alu(info, R, mx["stage_ms"][3]) if mx["stage_ms"][3] > 0.01 else None,
         "matvec_roofline": {
             "algorithmic_bytes": total_bytes,
             "achieved_GBs": total_bytes / (mx["ms_per_step"] * 1e-3) / 1e9,
