@@ -169,6 +169,14 @@ def test_matvec_mixed(name):
         assert rel(y[r], ref32[r]) <= 2e-5
         assert rel_max(y[r], ref32[r]) <= 2e-5
     assert rel(y, ref) <= 1e-4
+    # the solver's form: the same c64 arithmetic on c128 vectors, narrowed as
+    # x is read and widened as y is written, so equal to the c64 product bit
+    # for bit
+    x64 = x.astype(np.complex64).astype(np.complex128)
+    y_io = c.plan.matvec(torch.from_numpy(x64).cuda(), A.AIM_MIXED_IO64).cpu().numpy()
+    assert np.array_equal(y_io, y)
+    for r in range(2):
+        assert rel_max(y_io[r], ref32[r]) <= 2e-5
 
 
 @pytest.mark.parametrize("name,plane", [("plate1", 1), ("plate2j_m4", 2), ("plate1_m5", -1),
@@ -290,9 +298,10 @@ def test_products_with_changing_right_hand_side_counts(name):
         ref = oaim.matvec_fft(c.op, x)
         y = c.plan.matvec(torch.from_numpy(x).cuda(), A.AIM_FP64).cpu().numpy()
         y32 = c.plan.matvec(torch.from_numpy(x).cuda(), A.AIM_MIXED_IO64).cpu().numpy()
+        ref32 = oaim.matvec_fft(c.op, x.astype(np.complex64).astype(np.complex128))
         for k in range(r):
             assert rel(y[k], ref[k]) <= 1e-10, (r, k)
-            assert rel(y32[k], ref[k]) <= 1e-4, (r, k)
+            assert rel_max(y32[k], ref32[k]) <= 2e-5, (r, k)
 
 
 def _reference_stages(c, x):
@@ -444,9 +453,10 @@ def test_product_after_inspection_on_an_l_shaped_plate():
     ref = oaim.matvec_fft(op, x)
     y = plan.matvec(torch.from_numpy(x).cuda(), A.AIM_FP64).cpu().numpy()
     y32 = plan.matvec(torch.from_numpy(x).cuda(), A.AIM_MIXED_IO64).cpu().numpy()
+    ref32 = oaim.matvec_fft(op, x.astype(np.complex64).astype(np.complex128))
     for r in range(2):
         assert rel_max(y[r], ref[r]) <= 1e-10
-        assert rel(y32[r], ref[r]) <= 1e-4
+        assert rel_max(y32[r], ref32[r]) <= 2e-5
     plan.close()
 
 
