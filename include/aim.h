@@ -95,7 +95,11 @@ typedef struct {
  * cfie_alpha          with AIM_FLAG_CFIE: the combination parameter alpha in
  *                     [0, 1] of alpha EFIE + (1 - alpha) eta MFIE (the paper
  *                     uses 0.6 for its closed scatterers, Section 2.2);
- *                     ignored otherwise */
+ *                     ignored otherwise
+ * quad_points         points of the triangle quadrature of the projection,
+ *                     the near-zone fill, the excitation and the far field:
+ *                     7 (the paper's rule, Section 2.2; degree 5) or 0 (the
+ *                     same); other values give AIM_ERR_ARG */
 typedef struct {
   double h_lambda;
   int32_t order;
@@ -104,6 +108,8 @@ typedef struct {
   int32_t flags;
   int32_t tuning;
   double cfie_alpha;
+  int32_t quad_points;
+  int32_t reserved;
 } aim_params;
 
 #define AIM_FLAG_NO_MIXED 1 /* keep only FP64 operator data (AIM_MIXED -> AIM_ERR_STATE) */

@@ -66,7 +66,7 @@ class AimMesh(ctypes.Structure):
 class AimParams(ctypes.Structure):
     _fields_ = [("h_lambda", c_double), ("order", c_int32), ("fft_min_pad", c_int32),
                 ("near_radius_lambda", c_double), ("flags", c_int32), ("tuning", c_int32),
-                ("cfie_alpha", c_double)]
+                ("cfie_alpha", c_double), ("quad_points", c_int32), ("reserved", c_int32)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_void_p, c_size_t, c_void_p)
@@ -204,7 +204,7 @@ def _params(h_lambda, order, near_radius_lambda, fft_min_pad=0, flags=0, cfie_al
     rows = {0: 0, 128: 1, 64: 2}[int(tile_rows)]
     return AimParams(float(h_lambda), int(order), int(fft_min_pad), float(near_radius_lambda),
                      int(flags), int(xy_groups) | (rows << 8),
-                     float(cfie_alpha) if cfie_alpha is not None else 0.0)
+                     float(cfie_alpha) if cfie_alpha is not None else 0.0, 7, 0)
 
 
 def _waves(waves):

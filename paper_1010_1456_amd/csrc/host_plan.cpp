@@ -58,6 +58,7 @@ void host_plan_build(const aim_mesh &m, const aim_params &p, HostPlan *hp) {
   if (m.nv <= 0 || m.nt <= 0 || !m.verts || !m.tris) fail_arg("empty mesh");
   if (!(p.h_lambda > 0)) fail_arg("h_lambda must be > 0");
   if (p.order < 1 || p.order > 5) fail_arg("order must be in 1..5");
+  if (p.quad_points != 0 && p.quad_points != 7) fail_arg("quad_points must be 7 (or 0)");
   if (!(p.near_radius_lambda >= 0)) fail_arg("near_radius_lambda must be >= 0");
   const bool cfie_all = (p.flags & AIM_FLAG_CFIE) != 0;
   const bool cfie_closed = (p.flags & AIM_FLAG_CFIE_CLOSED) != 0;

@@ -103,6 +103,28 @@ def test_error_paths():
     assert e.value.status == lib_aim.AIM_ERR_MESH
 
 
+def test_quadrature_points_parameter():
+    """aim_params.quad_points: the paper's 7-point rule (7, or 0 for the
+    same); any other count is refused before any work."""
+    import ctypes
+
+    L = lib_aim.lib()
+    m = plate_mesh(1.0, 0.3e9)
+    keep = []
+    ms = lib_aim._mesh_struct(m.verts, m.tris, m.freq_hz, keep)
+    for q, want in ((7, lib_aim.AIM_OK), (0, lib_aim.AIM_OK), (3, lib_aim.AIM_ERR_ARG),
+                    (6, lib_aim.AIM_ERR_ARG), (-7, lib_aim.AIM_ERR_ARG)):
+        p = lib_aim._params(0.1, 2, 0.3)
+        p.quad_points = q
+        hp = ctypes.c_void_p()
+        st = L.aim_host_plan_build(ctypes.byref(ms), ctypes.byref(p), ctypes.byref(hp))
+        assert st == want, (q, st)
+        if st == lib_aim.AIM_OK:
+            L.aim_host_plan_destroy(hp)
+        else:
+            assert "quad_points" in L.aim_last_error().decode()
+
+
 def test_binding_layouts_and_constants_match_header(tmp_path):
     """The ctypes structures have the sizes and field offsets of the C
     declarations, and every #define the binding mirrors has the same value."""
