@@ -122,9 +122,11 @@ def ingest_pmc(fetch_csv, write_csv, workload):
         print(f"  {k}: read {v['read_bytes'] / 1e6:.1f} MB, write {v['write_bytes'] / 1e6:.1f} MB")
 
 
-def measured_traffic(workload, kernel_prefix):
+def measured_traffic(workload, kernel_prefix, row=None):
     """HBM bytes per launch of the kernel from the committed counter summary, or
-    None when there is none or the kernel sources changed since it was taken."""
+    None when there is none or the kernel sources changed since it was taken.
+    row: the tile-row variant (bytes) of the x and strided passes in use (the
+    counter runs also see the set-up tuner's other variant)."""
     path = os.path.join(PROFILES, f"{workload}_kernel_traffic.json")
     if not os.path.exists(path):
         return None
@@ -132,8 +134,10 @@ def measured_traffic(workload, kernel_prefix):
         t = json.load(f)
     if t.get("sources_sha256") != sources_digest():
         return None
-    hits = [v for k, v in t["kernels"].items() if k.startswith(kernel_prefix)]
-    return float(hits[0]["bytes"]) if len(hits) == 1 else None
+    hits = [k for k in t["kernels"] if k.startswith(kernel_prefix)]
+    if len(hits) > 1 and row is not None:
+        hits = [k for k in hits if k.endswith(f", {int(row)}>")]
+    return float(t["kernels"][hits[0]]["bytes"]) if len(hits) == 1 else None
 
 
 def stage_bytes(info, mesh, nrhs, s_grid, s_real, s_x, s_y, path):
@@ -718,7 +722,9 @@ def main(argv=None):
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(args.workload, "k_fft_xy<float" if piped and d == 2
-                                        else stage_kernel(d, fused)),
+                                        else stage_kernel(d, fused),
+                                        row=(info["tile_bytes"][0][1][0] if d == 3 else
+                                             info["tile_bytes"][0][1][1] if d in (2, 4) else None)),
             "algorithmic_bytes_per_launch": float(mx["bytes"][d]),
             "avg_launch_ms": float(mx["stage_ms"][d]),
             "copy_GBs": copy_gbs,
