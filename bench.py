@@ -599,6 +599,9 @@ def main(argv=None):
                     help="the EFIE on every scatterer (closed ones too)")
     ap.add_argument("--xy-groups", type=int, default=0, choices=[0, 1, 2, 4],
                     help="field groups of the pipelined y / x / y passes (0: chosen at set-up)")
+    ap.add_argument("--member", type=int, default=None,
+                    help="with a batch workload: time one of its scatterers alone "
+                         "(same right-hand sides per scatterer)")
     ap.add_argument("--tile-rows", type=int, default=0, choices=[0, 64, 128],
                     help="bytes of grid lines per x / y pass tile (0: chosen at set-up)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -647,6 +650,10 @@ def main(argv=None):
         cfg["order"] = args.order
     log(f"[bench] meshing {args.workload}")
     meshes = config_meshes(args.workload)
+    if args.member is not None:  # one scatterer of a batch on its own
+        if not 0 <= args.member < len(meshes):
+            raise SystemExit(f"--member: {args.workload} has {len(meshes)} scatterers")
+        meshes = [meshes[args.member]]
     mesh = meshes[0]
     torch.cuda.set_device(0)
     copy_gbs = copy_bandwidth()
@@ -696,7 +703,9 @@ def main(argv=None):
         "dtype": "c64",
         "data": "synthetic",
         "config": {
-            "workload": (f"{args.workload}: " + WORKLOAD_TEXT[args.workload]
+            "workload": (f"{args.workload}"
+                         + (f" member {args.member} ({mesh.name}) alone" if args.member is not None else "")
+                         + ": " + WORKLOAD_TEXT[args.workload]
                          + f"; {' and '.join(forms)}-AIM h={cfg['h_lambda']} lambda, M={cfg['order']} "
                          f"({(cfg['order'] + 1) ** 3}-node stencils), near radius "
                          f"{cfg['near_radius_lambda']} lambda; N={n}, grid "
