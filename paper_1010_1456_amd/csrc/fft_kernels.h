@@ -579,10 +579,11 @@ __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int 
           lds[((p - p0) * LM + beta + RM) * B + b] = vb[p];
         });
       __syncthreads();
+      const V *rowp = lds + ((h ? beta - S1 : beta) * R0) * B + b;
       if (act && (h ? beta >= S1 : beta < S1))
         static_for<R0>([&](auto q_) AIM_AI {
           constexpr int q = decltype(q_)::value;
-          w[q] = lds[((beta - p0) * R0 + q) * B + b];
+          w[q] = rowp[q * B];
         });
       if constexpr (h == 0) __syncthreads();
     });
@@ -613,10 +614,13 @@ __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int 
           lds[((p - p0) * Mp0 + beta) * B + b] = v0[p];
         });
       __syncthreads();
+      // (the row's base as its own non-negative index, so the element offsets
+      // fold into the LDS instructions)
+      const V *rowp = lds + ((h ? j - S0 : j) * RM) * B + b;
       if (act_mid && (h ? j >= S0 : j < S0))
         static_for<RM>([&](auto q_) AIM_AI {
           constexpr int q = decltype(q_)::value;
-          v[q] = lds[((j - p0) * RM + q) * B + b];
+          v[q] = rowp[q * B];
         });
       __syncthreads();
     };
@@ -651,10 +655,11 @@ __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int 
           lds[((p - p0) * LM + j) * B + b] = v[p];
         });
       __syncthreads();
+      const V *rowp = lds + ((h ? beta - S1 : beta) * R0) * B + b;
       if (act_last && (h ? beta >= S1 : beta < S1))
         static_for<R0>([&](auto q_) AIM_AI {
           constexpr int q = decltype(q_)::value;
-          w[q] = lds[((beta - p0) * R0 + q) * B + b];
+          w[q] = rowp[q * B];
         });
       if constexpr (h == 0) __syncthreads();
     };
