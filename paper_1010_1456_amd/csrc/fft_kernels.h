@@ -170,8 +170,13 @@ __global__ void __launch_bounds__((threads_contig<T, PC>()))
     // and range tables are read for every thread; nothing is loaded or
     // stored for them)
     const int64_t Lc = active ? line0 + b : lines - 1;
-    const V *gin = in + contig_base(imap, Lc);
-    V *gout = out + contig_base(omap, Lc);
+    // line bases only where the stage touches global memory; element offsets
+    // within a line fit 32 bits (checked by the launcher)
+    const V *gin = nullptr;
+    V *gout = nullptr;
+    if constexpr (first) gin = in + contig_base(imap, Lc);
+    if constexpr (last) gout = out + contig_base(omap, Lc);
+    const int es_in = (int)imap.es, es_out = (int)omap.es;
     V *ll = lds + b * LS;
     (void)tw;
     int in_lo = 0, in_hi = n_in, out_lo = 0, out_hi = n_out;
@@ -187,12 +192,12 @@ __global__ void __launch_bounds__((threads_contig<T, PC>()))
     }
     auto ld = [&](int i) AIM_AI -> V {
       if constexpr (first)
-        return (i >= in_lo && i < in_hi) ? gin[i * imap.es] : mk<V>((T)0, (T)0);
+        return (i >= in_lo && i < in_hi) ? gin[i * es_in] : mk<V>((T)0, (T)0);
       else return ll[i];
     };
     auto st = [&](int i, V v) AIM_AI {
       if constexpr (last) {
-        if (i >= out_lo && i < out_hi) gout[i * omap.es] = v;
+        if (i >= out_lo && i < out_hi) gout[i * es_out] = v;
       } else {
         ll[i] = v;
       }
@@ -836,6 +841,10 @@ void launch_contig(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64_t lin
       (B < std::max(imap.fin, omap.fin)) ? (blocks + kXcd - 1) / kXcd : 0;
   const int64_t launched = slots ? slots * kXcd : blocks;
   if (launched > INT32_MAX) throw Error(AIM_ERR_ARG, "contiguous pass: too many lines");
+  // 32-bit line arithmetic and element offsets in the kernel
+  if (contig_line_bound(imap, lines) >= INT32_MAX || contig_line_bound(omap, lines) >= INT32_MAX ||
+      (int64_t)PC::P * std::max(imap.es, omap.es) >= INT32_MAX)
+    throw Error(AIM_ERR_ARG, "contiguous pass: lines or line lengths beyond 32-bit offsets");
   const bool pr = pass_prunable<PC>(inverse, n_in, n_out);
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)launched), dim3(threads), lds, s, in, out, n_in,

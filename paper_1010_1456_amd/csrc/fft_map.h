@@ -80,22 +80,35 @@ struct ContigMap {
   // given, sel index l) of field f starts at f fs + l ls; per is unused
   int64_t fin = 0;
 };
+// Pass lines, and lines of the full numbering, stay below 2^31 (the launcher
+// checks it), so the line arithmetic divides in 32 bits; only the element
+// offsets are 64-bit.
 // index into sel / range of pass line L
 __host__ __device__ inline int64_t sel_index(const ContigMap &m, int64_t L) {
-  return m.fin ? L / m.fin : L % m.nsel;
+  const uint32_t Lu = (uint32_t)L;
+  return m.fin ? (int64_t)(Lu / (uint32_t)m.fin) : (int64_t)(Lu % (uint32_t)m.nsel);
 }
 __host__ __device__ inline int64_t contig_base(const ContigMap &m, int64_t L) {
+  const uint32_t Lu = (uint32_t)L;
   if (m.fin) {
-    const int64_t f = L % m.fin, l = L / m.fin;
-    return f * m.fs + (m.sel ? (int64_t)m.sel[l] : l) * m.ls;
+    const uint32_t fin = (uint32_t)m.fin, l = Lu / fin, f = Lu - l * fin;
+    return (int64_t)f * m.fs + (m.sel ? (int64_t)m.sel[l] : (int64_t)l) * m.ls;
   }
+  uint32_t line = Lu;
   if (m.sel) {
-    const int64_t f = L / m.nsel;
-    L = f * m.sper + m.sel[L - f * m.nsel];
+    const uint32_t ns = (uint32_t)m.nsel, f = Lu / ns;
+    line = f * (uint32_t)m.sper + (uint32_t)m.sel[Lu - f * ns];
   }
-  if (m.per == 0) return L * m.ls;
-  const int64_t f = L / m.per;
-  return f * m.fs + (L - f * m.per) * m.ls;
+  if (m.per == 0) return (int64_t)line * m.ls;
+  const uint32_t per = (uint32_t)m.per, f = line / per;
+  return (int64_t)f * m.fs + (int64_t)(line - f * per) * m.ls;
+}
+// the largest line index of the full numbering that pass lines 0 .. lines - 1
+// reach through m (host side, for the launcher's 32-bit check)
+inline int64_t contig_line_bound(const ContigMap &m, int64_t lines) {
+  if (m.fin) return lines;
+  if (m.sel) return (lines / m.nsel + 1) * m.sper;
+  return lines;
 }
 // lines ls apart, elements adjacent
 inline ContigMap contig_map(int64_t ls) { return ContigMap{0, 0, ls, 1}; }
