@@ -227,8 +227,9 @@ __device__ __forceinline__ void strided_body(const cx<T> *__restrict__ in, cx<T>
   V *lds = reinterpret_cast<V *>(smem_raw);
   constexpr int P = PC::P;
   constexpr int B = tile_strided<T, PC, ROW>();
-  const int64_t o = vb / ntile;
-  const int64_t c0 = (vb % ntile) * B;
+  const int vt = (int)vb;  // < 2^31 (launch size)
+  const int o = vt / ntile;
+  const int c0 = (vt - o * ntile) * B;
   const int b = threadIdx.x % B;
   const int beta = threadIdx.x / B;
   const bool line_ok = (c0 + b < inner);
@@ -243,12 +244,12 @@ __device__ __forceinline__ void strided_body(const cx<T> *__restrict__ in, cx<T>
   // element ranges of this line (all of it without a range table)
   int in_lo = 0, in_hi = n_in, out_lo = 0, out_hi = n_out;
   if (imap.range) {
-    const int r = (int)(o % imap.range_rows);
+    const int r = o % imap.range_rows;
     in_lo = imap.range[2 * r];
     in_hi = min(n_in, imap.range[2 * r + 1]);
   }
   if (omap.range) {
-    const int r = (int)(o % omap.range_rows);
+    const int r = o % omap.range_rows;
     out_lo = omap.range[2 * r];
     out_hi = min(n_out, omap.range[2 * r + 1]);
   }
@@ -868,7 +869,8 @@ void launch_strided_rows(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64
   const int64_t blocks = outer * ntile;
   const int64_t slots = ROW < 128 ? (blocks + kXcd - 1) / kXcd : 0;
   const int64_t launched = ROW < 128 ? slots * kXcd : blocks;
-  if (launched > INT32_MAX) throw Error(AIM_ERR_ARG, "strided pass: too many tiles");
+  if (launched > INT32_MAX || inner >= INT32_MAX)
+    throw Error(AIM_ERR_ARG, "strided pass: too many tiles or lines");
   const bool pr = pass_prunable<PC>(inverse, n_in, n_out);
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)launched), dim3(threads), lds, s, in, out, n_in,

@@ -29,11 +29,14 @@ inline LineMap with_range(LineMap m, const int32_t *range, int rows) {
   m.range_rows = rows;
   return m;
 }
+// (outer and inner line indices stay below 2^31, checked by the launcher:
+// the index arithmetic divides in 32 bits, only the offsets are 64-bit)
 __host__ __device__ inline int64_t line_base(const LineMap &m, int64_t o, int64_t c) {
-  const int64_t oh = o / m.lo_count, ol = o - oh * m.lo_count;
-  const int64_t b = oh * m.hi + ol * m.lo;
+  const uint32_t ou = (uint32_t)o, lc = (uint32_t)m.lo_count, oh = ou / lc, ol = ou - oh * lc;
+  const int64_t b = (int64_t)oh * m.hi + (int64_t)ol * m.lo;
   if (m.blk == 0) return b + c;
-  return b + (c / m.blk) * m.bstr + c % m.blk;
+  const uint32_t cu = (uint32_t)c, bk = (uint32_t)m.blk, cb = cu / bk;
+  return b + (int64_t)cb * m.bstr + (int64_t)(cu - cb * bk);
 }
 __host__ __device__ inline int64_t line_elem(const LineMap &m) { return m.blk == 0 ? m.elem : m.blk; }
 
