@@ -21,6 +21,7 @@
 #pragma once
 
 #include <algorithm>
+#include <type_traits>
 
 #include "aim_internal.h"
 #include "fft_core.h"
@@ -41,21 +42,31 @@ constexpr int kXcd = 8;
 using u32x2 = unsigned int __attribute__((ext_vector_type(2)));
 using u32x4 = unsigned int __attribute__((ext_vector_type(4)));
 
-// The y passes load and store the grid non-temporally (the "nt" cache
-// policy: each element is streamed through the caches once); measured on the
-// 8-lambda sphere, forward y 0.164 -> 0.150 ms, inverse y 0.151 -> 0.138 ms
-// (c64). The z passes keep the default policy: their strided stores measured
-// slower with it (forward z 0.067 -> 0.099 ms).
-template <typename V>
+// Passes over a grid larger than the 256 MB last-level cache load and store it
+// non-temporally (the "nt" cache policy: each element is streamed through the
+// caches once): the y passes, and the x pass in the kz-blocked layout.
+// Measured on the 8-lambda sphere (541 MB per pass, c64): forward y 0.164 ->
+// 0.150 ms, x pass 0.355 -> 0.325, inverse y 0.151 -> 0.138. Smaller grids
+// keep the default policy, under which a pass can find its input still in that
+// cache (the uneven batch, whose small members' grids fit: c64 product 2.365
+// ms with the nt policy on every grid, 2.336 ms with it on the large ones
+// only). The z passes always keep the default: their strided stores measured
+// slower with the nt policy (8-lambda sphere, forward z 0.067 -> 0.099 ms).
+constexpr uint64_t kStreamBytes = 256ull << 20;
+template <bool NT, typename V>
 __device__ __forceinline__ V stream_load(const V *p) {
-  if constexpr (sizeof(V) == 8)
+  if constexpr (!NT)
+    return *p;
+  else if constexpr (sizeof(V) == 8)
     return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p)));
   else
     return __builtin_bit_cast(V, __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p)));
 }
-template <typename V>
+template <bool NT, typename V>
 __device__ __forceinline__ void stream_store(V *p, V v) {
-  if constexpr (sizeof(V) == 8)
+  if constexpr (!NT)
+    *p = v;
+  else if constexpr (sizeof(V) == 8)
     __builtin_nontemporal_store(__builtin_bit_cast(u32x2, v), reinterpret_cast<u32x2 *>(p));
   else
     __builtin_nontemporal_store(__builtin_bit_cast(u32x4, v), reinterpret_cast<u32x4 *>(p));
@@ -239,7 +250,7 @@ __global__ void __launch_bounds__((threads_contig<T, PC>()))
 
 // One work-group of a strided pass: tile vb = o ntile + (c0 / B) covers the
 // B lines (o, c0 .. c0 + B - 1).
-template <typename T, bool INV, bool PR, class PC, int ROW = 128>
+template <typename T, bool INV, bool PR, class PC, int ROW = 128, bool NT = true>
 __device__ __forceinline__ void strided_body(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
                                              int n_in, int n_out, int64_t inner, int ntile,
                                              const LineMap &imap, const LineMap &omap,
@@ -287,13 +298,13 @@ __device__ __forceinline__ void strided_body(const cx<T> *__restrict__ in, cx<T>
     const bool active = line_ok && (beta < nb);
     auto ld = [&](int i) AIM_AI -> V {
       if constexpr (first)
-        return (i >= in_lo && i < in_hi) ? stream_load(&gin_b[(i - beta) * in_elem])
+        return (i >= in_lo && i < in_hi) ? stream_load<NT>(&gin_b[(i - beta) * in_elem])
                                          : mk<V>((T)0, (T)0);
       else return lds[i * B + b];
     };
     auto st = [&](int i, V v) AIM_AI {
       if constexpr (last) {
-        if (i >= out_lo && i < out_hi) stream_store(&gout_b[(i - beta) * out_elem], v);
+        if (i >= out_lo && i < out_hi) stream_store<NT>(&gout_b[(i - beta) * out_elem], v);
       } else {
         lds[i * B + b] = v;
       }
@@ -311,7 +322,7 @@ __device__ __forceinline__ void strided_body(const cx<T> *__restrict__ in, cx<T>
   });
 }
 
-template <typename T, bool INV, bool PR, class PC, int ROW>
+template <typename T, bool INV, bool PR, class PC, int ROW, bool NT>
 __global__ void __launch_bounds__((threads_strided<T, PC, ROW>()))
     k_fft_strided(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, int n_in, int n_out,
                   int64_t inner, int ntile, LineMap imap, LineMap omap,
@@ -324,7 +335,7 @@ __global__ void __launch_bounds__((threads_strided<T, PC, ROW>()))
     vb = (int64_t)(blockIdx.x % kXcd) * slots + blockIdx.x / kXcd;
     if (vb >= tiles) return;  // the whole work-group
   }
-  strided_body<T, INV, PR, PC, ROW>(in, out, n_in, n_out, inner, ntile, imap, omap, tw, vb);
+  strided_body<T, INV, PR, PC, ROW, NT>(in, out, n_in, n_out, inner, ntile, imap, omap, tw, vb);
 }
 
 // x pass: forward transform along x, spectrum multiply and inverse transform
@@ -414,7 +425,7 @@ constexpr int mid_min_waves() {
 }
 
 // One work-group of the x pass: vb is the launch's block number (XCD vb % 8).
-template <typename T, class PC, bool KYL, int ROW = 128, bool WIDE = false>
+template <typename T, class PC, bool KYL, int ROW = 128, bool WIDE = false, bool NT = true>
 __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int nfield, int Py,
                                          int Pz, int ntile, int slots, int Hy, int Hz,
                                          const cx<T> *__restrict__ ghat,
@@ -428,11 +439,10 @@ __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int 
   constexpr int B = ML::B;  // lines of the work-group (consecutive along the tile axis)
   static_assert(!WIDE || (mid_wide_plan<PC>() && ML::split), "wide work-groups");
   constexpr uint32_t SV = sizeof(V);
-  // the lines are loaded and stored non-temporally (buffer cache policy
-  // bit 1) in the kz-blocked layout (8-lambda sphere: 0.355 -> 0.325 ms, c64);
-  // the thin layout of the plates keeps the default policy (128-lambda plate:
-  // 0.165 -> 0.405 ms with it)
-  constexpr int kNtAux = KYL ? 0 : 2;
+  // NT: the lines are loaded and stored non-temporally (buffer cache policy
+  // bit 1); the thin layout of the plates keeps the default policy
+  // (128-lambda plate: x pass 0.165 -> 0.405 ms with the nt policy)
+  constexpr int kNtAux = (NT && !KYL) ? 2 : 0;
   // a line holds at most P/2 sources (n_x <= P/2 for even P, checked by the
   // launcher) and only its first P/2 outputs are kept: with an even first
   // radix the forward transform's first stage skips the zero upper half of
@@ -789,14 +799,14 @@ __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int 
   }
 }
 
-template <typename T, class PC, bool KYL, int ROW>
+template <typename T, class PC, bool KYL, int ROW, bool NT>
 __global__ void __launch_bounds__((threads_mid<T, PC, ROW, mid_wide_plan<PC>()>()),
                                   (mid_min_waves<T, PC, ROW, mid_wide_plan<PC>()>()))
     k_fft_mid(cx<T> *__restrict__ data, int n_x, int nfield, int Py, int Pz, int ntile, int slots,
               int Hy, int Hz, const cx<T> *__restrict__ ghat, const cx<T> *__restrict__ tw, int blk,
               int64_t fstride) {
-  mid_body<T, PC, KYL, ROW, mid_wide_plan<PC>()>(data, n_x, nfield, Py, Pz, ntile, slots, Hy, Hz,
-                                                 ghat, tw, blk, fstride, blockIdx.x);
+  mid_body<T, PC, KYL, ROW, mid_wide_plan<PC>(), NT>(data, n_x, nfield, Py, Pz, ntile, slots, Hy,
+                                                     Hz, ghat, tw, blk, fstride, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -901,14 +911,23 @@ void launch_strided_rows(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64
   if (launched > INT32_MAX || inner >= INT32_MAX)
     throw Error(AIM_ERR_ARG, "strided pass: too many tiles or lines");
   const bool pr = pass_prunable<PC>(inverse, n_in, n_out);
+  const bool nt =
+      (uint64_t)outer * (uint64_t)inner * (uint64_t)std::max(n_in, n_out) * sizeof(cx<T>) >
+      kStreamBytes;
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)launched), dim3(threads), lds, s, in, out, n_in,
                        n_out, inner, ntile, imap, omap, tw, blocks, slots);
   };
-  if (inverse)
-    pr ? go(k_fft_strided<T, true, true, PC, ROW>) : go(k_fft_strided<T, true, false, PC, ROW>);
-  else
-    pr ? go(k_fft_strided<T, false, true, PC, ROW>) : go(k_fft_strided<T, false, false, PC, ROW>);
+  auto pick = [&](auto nt_) {
+    constexpr bool NT = decltype(nt_)::value;
+    if (inverse)
+      pr ? go(k_fft_strided<T, true, true, PC, ROW, NT>)
+         : go(k_fft_strided<T, true, false, PC, ROW, NT>);
+    else
+      pr ? go(k_fft_strided<T, false, true, PC, ROW, NT>)
+         : go(k_fft_strided<T, false, false, PC, ROW, NT>);
+  };
+  nt ? pick(std::true_type{}) : pick(std::false_type{});
   LAUNCHCHECK();
 }
 
@@ -948,14 +967,16 @@ void launch_mid_rows(cx<T> *data, int n_x, int nfield, int Py, int Pz, int Hy, i
   const int64_t items = 2 * ((int64_t)Pf / 2 + 1) * ntile * nfield;
   const int64_t slots = (items + kXcd - 1) / kXcd;
   if (slots * kXcd > INT32_MAX) throw Error(AIM_ERR_ARG, "x pass: too many tiles");
+  const bool nt =
+      (uint64_t)nfield * (uint64_t)Py * (uint64_t)Pz * (uint64_t)n_x * sizeof(cx<T>) > kStreamBytes;
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3((unsigned)(slots * kXcd)), dim3(threads), lds, s, data, n_x,
+                       nfield, Py, Pz, ntile, (int)slots, Hy, Hz, ghat, tw, blk, fstride);
+  };
   if (kyl)
-    hipLaunchKernelGGL((k_fft_mid<T, PC, true, ROW>), dim3((unsigned)(slots * kXcd)),
-                       dim3(threads), lds, s, data, n_x, nfield, Py, Pz, ntile, (int)slots, Hy, Hz,
-                       ghat, tw, blk, fstride);
+    go(k_fft_mid<T, PC, true, ROW, false>);
   else
-    hipLaunchKernelGGL((k_fft_mid<T, PC, false, ROW>), dim3((unsigned)(slots * kXcd)),
-                       dim3(threads), lds, s, data, n_x, nfield, Py, Pz, ntile, (int)slots, Hy, Hz,
-                       ghat, tw, blk, fstride);
+    nt ? go(k_fft_mid<T, PC, false, ROW, true>) : go(k_fft_mid<T, PC, false, ROW, false>);
   LAUNCHCHECK();
 }
 
