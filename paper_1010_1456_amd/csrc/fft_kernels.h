@@ -817,7 +817,8 @@ __global__ void __launch_bounds__((threads_mid<T, PC, ROW, mid_wide_plan<PC>()>(
 // x pass of group t - 1 together with the forward y pass of group t and the
 // inverse y pass of group t - 2 (G + 2 launches in all). The launch's blocks
 // come in runs of 8 (one per XCD); each run has one role, and the roles are
-// spread evenly over the launch so every CU mixes them.
+// spread evenly over the launch so every CU mixes them. All roles use the nt
+// cache policy (the set-up keeps this launch only where it times faster).
 template <typename T>
 struct XyStrided {
   const cx<T> *in;
@@ -911,9 +912,12 @@ void launch_strided_rows(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64
   if (launched > INT32_MAX || inner >= INT32_MAX)
     throw Error(AIM_ERR_ARG, "strided pass: too many tiles or lines");
   const bool pr = pass_prunable<PC>(inverse, n_in, n_out);
+  // 64-byte tiles keep the default policy: the two tiles of a 128-byte line
+  // meet in L2, which the nt policy would evict between them
   const bool nt =
+      ROW == 128 &&
       (uint64_t)outer * (uint64_t)inner * (uint64_t)std::max(n_in, n_out) * sizeof(cx<T>) >
-      kStreamBytes;
+          kStreamBytes;
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)launched), dim3(threads), lds, s, in, out, n_in,
                        n_out, inner, ntile, imap, omap, tw, blocks, slots);
@@ -927,7 +931,10 @@ void launch_strided_rows(const cx<T> *in, cx<T> *out, int n_in, int n_out, int64
       pr ? go(k_fft_strided<T, false, true, PC, ROW, NT>)
          : go(k_fft_strided<T, false, false, PC, ROW, NT>);
   };
-  nt ? pick(std::true_type{}) : pick(std::false_type{});
+  if constexpr (ROW == 128)
+    nt ? pick(std::true_type{}) : pick(std::false_type{});
+  else
+    pick(std::false_type{});
   LAUNCHCHECK();
 }
 
@@ -967,16 +974,20 @@ void launch_mid_rows(cx<T> *data, int n_x, int nfield, int Py, int Pz, int Hy, i
   const int64_t items = 2 * ((int64_t)Pf / 2 + 1) * ntile * nfield;
   const int64_t slots = (items + kXcd - 1) / kXcd;
   if (slots * kXcd > INT32_MAX) throw Error(AIM_ERR_ARG, "x pass: too many tiles");
-  const bool nt =
-      (uint64_t)nfield * (uint64_t)Py * (uint64_t)Pz * (uint64_t)n_x * sizeof(cx<T>) > kStreamBytes;
+  // the nt policy as in the y passes: 128-byte tiles of grids beyond the
+  // last-level cache
+  const uint64_t grid_bytes = (uint64_t)nfield * Py * Pz * n_x * sizeof(cx<T>);
+  const bool nt = ROW == 128 && grid_bytes > kStreamBytes;
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)(slots * kXcd)), dim3(threads), lds, s, data, n_x,
                        nfield, Py, Pz, ntile, (int)slots, Hy, Hz, ghat, tw, blk, fstride);
   };
   if (kyl)
     go(k_fft_mid<T, PC, true, ROW, false>);
-  else
+  else if constexpr (ROW == 128)
     nt ? go(k_fft_mid<T, PC, false, ROW, true>) : go(k_fft_mid<T, PC, false, ROW, false>);
+  else
+    go(k_fft_mid<T, PC, false, ROW, false>);
   LAUNCHCHECK();
 }
 
