@@ -136,7 +136,7 @@ def measured_traffic(workload, kernel_prefix, row=None):
         return None
     hits = [k for k in t["kernels"] if k.startswith(kernel_prefix)]
     if len(hits) > 1 and row is not None:
-        hits = [k for k in hits if k.endswith(f", {int(row)}>")]
+        hits = [k for k in hits if re.search(rf", {int(row)}(, (true|false))?>$", k)]
     return float(t["kernels"][hits[0]]["bytes"]) if len(hits) == 1 else None
 
 
