@@ -91,6 +91,13 @@ typedef struct {
  *                     bits 8-15 tile rows of the x and strided y passes
  *                               (aim_info.tile_bytes): 0 (pick), 1 (128-byte
  *                               rows), 2 (64-byte rows);
+ *                     bits 16-23 right-hand sides per mesh that the set-up
+ *                               times the variants with, 0 (= 1) to 64: the
+ *                               fastest variant depends on it (the passes
+ *                               of many right-hand sides stream grids
+ *                               larger than the GPU's last-level cache),
+ *                               so a caller that will apply the operator to
+ *                               R right-hand sides at a time passes R;
  *                     other values give AIM_ERR_ARG
  * cfie_alpha          with AIM_FLAG_CFIE: the combination parameter alpha in
  *                     [0, 1] of alpha EFIE + (1 - alpha) eta MFIE (the paper

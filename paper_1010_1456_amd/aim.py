@@ -196,14 +196,15 @@ def _mesh_struct(verts, tris, freq_hz, keep):
 
 
 def _params(h_lambda, order, near_radius_lambda, fft_min_pad=0, flags=0, cfie_alpha=None,
-            cfie_closed_only=False, xy_groups=0, tile_rows=0):
+            cfie_closed_only=False, xy_groups=0, tile_rows=0, tune_rhs=0):
     """tile_rows: 0 (chosen at set-up), 128 or 64 bytes of grid lines per
-    tile of the x and strided y passes."""
+    tile of the x and strided y passes. tune_rhs: right-hand sides per mesh
+    the set-up times the kernel variants with (0: one)."""
     if cfie_alpha is not None:
         flags |= AIM_FLAG_CFIE_CLOSED if cfie_closed_only else AIM_FLAG_CFIE
     rows = {0: 0, 128: 1, 64: 2}[int(tile_rows)]
     return AimParams(float(h_lambda), int(order), int(fft_min_pad), float(near_radius_lambda),
-                     int(flags), int(xy_groups) | (rows << 8),
+                     int(flags), int(xy_groups) | (rows << 8) | (int(tune_rhs) << 16),
                      float(cfie_alpha) if cfie_alpha is not None else 0.0, 7, 0)
 
 
@@ -274,11 +275,13 @@ class TorchAllocator:
 class Plan:
     """An AIM operator on the current GPU for one or more meshes.
 
-    meshes: list of (verts (nv,3) metres, tris (nt,3), freq_hz)."""
+    meshes: list of (verts (nv,3) metres, tris (nt,3), freq_hz).
+    tune_rhs: right-hand sides per mesh the set-up times the kernel variants
+    with (the number the products will apply the operator to; 0: one)."""
 
     def __init__(self, meshes, h_lambda=0.1, order=2, near_radius_lambda=0.3, fft_min_pad=0,
                  mixed=True, stream=None, cfie_alpha=None, cfie_closed_only=False, xy_groups=0,
-                 flags=0, tile_rows=0):
+                 flags=0, tile_rows=0, tune_rhs=0):
         import torch
 
         self._torch = torch
@@ -293,7 +296,7 @@ class Plan:
             arr[i] = _mesh_struct(v, t, f, keep)
         p = _params(h_lambda, order, near_radius_lambda, fft_min_pad,
                     int(flags) | (0 if mixed else AIM_FLAG_NO_MIXED), cfie_alpha, cfie_closed_only,
-                    xy_groups, tile_rows)
+                    xy_groups, tile_rows, tune_rhs)
         self._alloc = TorchAllocator(self.device)
         h = c_void_p()
         _check(L.aim_setup(arr, len(meshes), ctypes.byref(p), ctypes.byref(self._alloc.struct),

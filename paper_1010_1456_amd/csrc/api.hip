@@ -174,9 +174,11 @@ aim_status aim_setup(const aim_mesh *meshes, int32_t nmesh, const aim_params *p,
   if (nmesh < 1 || nmesh > AIM_MAX_MESH) return fail(AIM_ERR_ARG, "nmesh out of range");
   if (alloc && (!alloc->alloc || !alloc->free)) return fail(AIM_ERR_ARG, "incomplete allocator");
   {
-    const int g = p->tuning & 0xff, t = (p->tuning >> 8) & 0xff;
-    if ((p->tuning >> 16) != 0 || (g != 0 && g != 1 && g != 2 && g != 4) || t > 2)
-      return fail(AIM_ERR_ARG, "tuning: pipeline groups 0, 1, 2 or 4; tile rows 0, 1 or 2");
+    const int g = p->tuning & 0xff, t = (p->tuning >> 8) & 0xff, r = (p->tuning >> 16) & 0xff;
+    if ((p->tuning >> 24) != 0 || (g != 0 && g != 1 && g != 2 && g != 4) || t > 2 || r > 64)
+      return fail(AIM_ERR_ARG,
+                  "tuning: pipeline groups 0, 1, 2 or 4; tile rows 0, 1 or 2; right-hand sides "
+                  "0 to 64");
   }
   std::unique_ptr<aim_plan> pl(new aim_plan());
   if (alloc) {

@@ -588,3 +588,26 @@ def test_tuning_values_are_validated():
     h = ctypes.c_void_p()
     assert L.aim_setup(arr, 1, ctypes.byref(p), None, None, ctypes.byref(h)) == A.AIM_ERR_ARG
     assert h.value is None
+    for bad in (65 << 16, 1 << 24):  # tuning right-hand sides above 64; unused bits
+        p.tuning = bad
+        assert L.aim_setup(arr, 1, ctypes.byref(p), None, None, ctypes.byref(h)) == A.AIM_ERR_ARG
+        assert h.value is None
+
+
+def test_tuning_with_several_right_hand_sides():
+    """Set-up timing its variants on 4 right-hand sides per mesh: the chosen
+    variants' products of 4 right-hand sides against the oracle."""
+    from paper_1010_1456_amd import aim as A
+
+    c = case("sphere05")
+    plan = A.Plan([(c.mesh.verts, c.mesh.tris, c.mesh.freq_hz)], order=c.order, tune_rhs=4)
+    x = random_current(c.rwg.n, nrhs=4, seed=114)
+    ref = oaim.matvec_fft(c.op, x)
+    y = plan.matvec(torch.from_numpy(x).cuda(), A.AIM_FP64).cpu().numpy()
+    x32 = x.astype(np.complex64)
+    ref32 = oaim.matvec_fft(c.op, x32.astype(np.complex128))
+    y32 = plan.matvec(torch.from_numpy(x32).cuda(), A.AIM_MIXED).cpu().numpy()
+    for r in range(4):
+        assert rel_max(y[r], ref[r]) <= 1e-10, r
+        assert rel_max(y32[r], ref32[r]) <= 2e-5, r
+    plan.close()
