@@ -429,7 +429,8 @@ template <typename T, class PC, bool KYL, int ROW = 128, bool WIDE = false, bool
 __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int nfield, int Py,
                                          int Pz, int ntile, int slots, int Hy, int Hz,
                                          const cx<T> *__restrict__ ghat,
-                                         const cx<T> *__restrict__ tw, int blk, int64_t fstride,
+                                         const cx<T> *__restrict__ tw, int64_t fstride,
+                                         const FastDiv &dfield, const FastDiv &dtile,
                                          int64_t vb) {
   using V = cx<T>;
   using ML = MidLds<T, PC, ROW, WIDE>;
@@ -460,9 +461,9 @@ __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int 
   // mirror Pf - ff (m = 1), which reads the same octant rows, tile kt.
   const int Pt = KYL ? Py : Pz, Pf = KYL ? Pz : Py;
   const int t = (int)(vb % kXcd) * slots + (int)(vb / kXcd);
-  const int field = t % nfield, tt = t / nfield;
+  const int tt = (int)fast_div((uint32_t)t, dfield), field = t - tt * nfield;
   const int m = tt & 1, rest = tt >> 1;
-  const int ff = rest / ntile;
+  const int ff = (int)fast_div((uint32_t)rest, dtile);
   const int kt = rest - ff * ntile;
   if (2 * ff > Pf) return;                      // padding: exit before any barrier
   if (m && (ff == 0 || 2 * ff == Pf)) return;  // its own mirror: m = 0 covers it
@@ -475,6 +476,9 @@ __device__ __forceinline__ void mid_body(cx<T> *__restrict__ data, int n_x, int 
   const int fl = (kl <= Pt - kl) ? kl : Pt - kl;
   const int fky = KYL ? fl : ff, fkz = KYL ? ff : fl;
   const int gplane = Hy * Hz;
+  // kz block of the kz-blocked layout: 128 bytes of consecutive kz (checked by
+  // the launchers)
+  constexpr int blk = kGridBlock<T>;
   const int es = KYL ? Py : Py * blk;  // elements between x and x + 1 of a line
   // field data: resource over the kz blocks of the work-group's lines (one kz
   // plane for KYL) of this field; its first line starts at byte t0, thread
@@ -803,10 +807,11 @@ template <typename T, class PC, bool KYL, int ROW, bool NT>
 __global__ void __launch_bounds__((threads_mid<T, PC, ROW, mid_wide_plan<PC>()>()),
                                   (mid_min_waves<T, PC, ROW, mid_wide_plan<PC>()>()))
     k_fft_mid(cx<T> *__restrict__ data, int n_x, int nfield, int Py, int Pz, int ntile, int slots,
-              int Hy, int Hz, const cx<T> *__restrict__ ghat, const cx<T> *__restrict__ tw, int blk,
-              int64_t fstride) {
+              int Hy, int Hz, const cx<T> *__restrict__ ghat, const cx<T> *__restrict__ tw,
+              int64_t fstride, FastDiv dfield, FastDiv dtile) {
   mid_body<T, PC, KYL, ROW, mid_wide_plan<PC>(), NT>(data, n_x, nfield, Py, Pz, ntile, slots, Hy,
-                                                     Hz, ghat, tw, blk, fstride, blockIdx.x);
+                                                     Hz, ghat, tw, fstride, dfield, dtile,
+                                                     blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -832,8 +837,9 @@ struct XyStrided {
 template <typename T>
 struct XyMid {
   cx<T> *data;  // first field of the group
-  int n_x, nfield, Py, Pz, ntile, slots, Hy, Hz, blk;
+  int n_x, nfield, Py, Pz, ntile, slots, Hy, Hz;
   int64_t fstride;
+  FastDiv dfield, dtile;
   int64_t nb;  // blocks of the x pass (slots * 8), 0: none in this launch
 };
 
@@ -863,7 +869,7 @@ __global__ void __launch_bounds__((threads_xy<T, PC>()), (sizeof(T) == 4 ? 4 : 3
   const int64_t v = (run - ylo) * kXcd + xcd;  // x runs keep the XCD of their block
   if (v < xm.nb)
     mid_body<T, PC, false>(xm.data, xm.n_x, xm.nfield, xm.Py, xm.Pz, xm.ntile, xm.slots, xm.Hy,
-                           xm.Hz, ghat, twx, xm.blk, xm.fstride, v);
+                           xm.Hz, ghat, twx, xm.fstride, xm.dfield, xm.dtile, v);
 }
 
 template <typename T, class PC>
@@ -958,8 +964,9 @@ void launch_mid_rows(cx<T> *data, int n_x, int nfield, int Py, int Pz, int Hy, i
   const bool kyl = blk == 0;
   if (PC::r(0) % 2 == 0 && 2 * n_x > PC::P)  // the half-pruned first/last stages need it
     throw Error(AIM_ERR_ARG, "x pass: more than P/2 sources on a line");
-  if (blk < 0 || (!kyl && (B <= blk ? blk % B : B % blk) != 0))
-    throw Error(AIM_ERR_ARG, "x pass: work-group lines and kz blocks do not tile");
+  if (blk < 0 || (!kyl && blk != kGridBlock<T>) ||
+      (!kyl && (B <= blk ? blk % B : B % blk) != 0))
+    throw Error(AIM_ERR_ARG, "x pass: kz block other than 128 bytes, or not tiled by the lines");
   // 32-bit buffer offsets: the kz blocks of a work-group (a kz plane) of a
   // field, and the octant
   const uint64_t wblocks = (!kyl && B > blk) ? (uint64_t)(B / blk) : 1;
@@ -977,10 +984,11 @@ void launch_mid_rows(cx<T> *data, int n_x, int nfield, int Py, int Pz, int Hy, i
   // the nt policy as in the y passes: 128-byte tiles of grids beyond the
   // last-level cache
   const uint64_t grid_bytes = (uint64_t)nfield * Py * Pz * n_x * sizeof(cx<T>);
+  const FastDiv dfield = make_fastdiv((uint32_t)nfield), dtile = make_fastdiv((uint32_t)ntile);
   const bool nt = ROW == 128 && grid_bytes > kStreamBytes;
   auto go = [&](auto kern) {
     hipLaunchKernelGGL(kern, dim3((unsigned)(slots * kXcd)), dim3(threads), lds, s, data, n_x,
-                       nfield, Py, Pz, ntile, (int)slots, Hy, Hz, ghat, tw, blk, fstride);
+                       nfield, Py, Pz, ntile, (int)slots, Hy, Hz, ghat, tw, fstride, dfield, dtile);
   };
   if (kyl)
     go(k_fft_mid<T, PC, true, ROW, false>);
@@ -1020,7 +1028,8 @@ void launch_xy(const cx<T> *gz, cx<T> *g2, cx<T> *g1, int Nx, int Ny, int F, int
   // pruned first / last stages: at most P/2 sources per x and y line
   if ((PRF || PRI) && (2 * Nx > PC::P || 2 * Ny > PC::P))
     throw Error(AIM_ERR_ARG, "y/x pipeline: more than P/2 sources on a line");
-  if (blk <= 0 || blk % B != 0) throw Error(AIM_ERR_ARG, "y/x pipeline: tile does not divide the kz block");
+  if (blk != kGridBlock<T> || blk % B != 0)
+    throw Error(AIM_ERR_ARG, "y/x pipeline: kz block other than 128 bytes, or not tiled");
   if ((uint64_t)Nx * Py * blk * sizeof(cx<T>) >= (1ull << 31) ||
       (uint64_t)Hy * Hz * (PC::P / 2 + 1) * sizeof(cx<T>) >= (1ull << 31))
     throw Error(AIM_ERR_ARG, "y/x pipeline: grid too large for 32-bit offsets");
@@ -1043,8 +1052,9 @@ void launch_xy(const cx<T> *gz, cx<T> *g2, cx<T> *g1, int Nx, int Ny, int F, int
       xm.slots = (int)slots;
       xm.Hy = Hy;
       xm.Hz = Hz;
-      xm.blk = blk;
       xm.fstride = V2;
+      xm.dfield = make_fastdiv((uint32_t)Fg);
+      xm.dtile = make_fastdiv((uint32_t)ntile);
       xm.nb = slots * kXcd;
     }
     XyStrided<T> yf{gz, g2, Ny, Py, Pz, ntile, m1y, m2, (int64_t)t * ynb, t < G ? ynb : 0};

@@ -29,6 +29,27 @@ inline LineMap with_range(LineMap m, const int32_t *range, int rows) {
   m.range_rows = rows;
   return m;
 }
+// Division of numerators below 2^31 by a run-time divisor d >= 1 as a
+// multiply-high, an add and a shift (the round-up method of Granlund and
+// Montgomery, "Division by invariant integers using multiplication", 1994):
+// with s = ceil(log2 d) and m = floor(2^32 (2^s - d) / d) + 1,
+// n / d = (mulhi(n, m) + n) >> s. A work-group-uniform numerator then divides
+// in scalar instructions instead of the vector ALU's reciprocal sequence.
+struct FastDiv {
+  uint32_t d = 1, m = 0, s = 0;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  while ((1ull << f.s) < d) ++f.s;
+  f.m = (uint32_t)((((1ull << f.s) - d) << 32) / d + 1);
+  return f;
+}
+__host__ __device__ inline uint32_t fast_div(uint32_t n, const FastDiv &f) {
+  const uint32_t h = (uint32_t)(((uint64_t)n * f.m) >> 32);
+  return (h + n) >> f.s;
+}
+
 // (outer and inner line indices stay below 2^31, checked by the launcher:
 // the index arithmetic divides in 32 bits, only the offsets are 64-bit)
 __host__ __device__ inline int64_t line_base(const LineMap &m, int64_t o, int64_t c) {

@@ -66,3 +66,19 @@ def test_line_maps_stay_in_bounds():
     for name, max_sel, nsel, max_first, max_last, limit in rows:
         assert int(max_sel) == int(nsel) - 1, name
         assert 0 <= int(max_first) and int(max_last) < int(limit), name
+
+
+def test_fast_division_matches_integer_division():
+    """The x pass divides its work number by the field and tile counts with a
+    multiply-high and a shift: it equals integer division for every divisor
+    and numerator the check program tries (all divisors up to 4096, powers of
+    two and their neighbours, random divisors up to 2^31 - 1; numerators at
+    multiples of the divisor and their neighbours, and random ones)."""
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "fastdiv_check")
+        subprocess.run([_hipcc(), "-O1", "-std=c++17", "-x", "hip", "--offload-arch=gfx950",
+                        "-I", CSRC, os.path.join(HERE, "fastdiv_check.cpp"), "-o", exe],
+                       check=True, capture_output=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    assert out[0] == "checked" and int(out[1]) > 1_000_000, out
+    assert out[2] == "mismatches" and int(out[3]) == 0, out
