@@ -151,7 +151,7 @@ struct MeshDev {
   int32_t *occ_yrange = nullptr;  // 2 Nx
   // per occupied z line: the z range [lo, hi) of its occupied nodes (the z
   // passes read and write only these elements of the grid side)
-  int32_t *occ_zrange = nullptr;  // 2 n_occ_lines
+  int32_t *occ_zrange = nullptr;  // 4 n_occ_lines: {lo, g0, g1, hi} per occupied line
   int32_t *ent_col = nullptr;   // n_entries
   double *lamT64 = nullptr;     // n_entries * 4
   float *lamT32 = nullptr;      // n_entries * 4

@@ -95,9 +95,9 @@ struct ContigMap {
   int64_t per, fs, ls, es;
   const int32_t *sel = nullptr;
   int64_t nsel = 0, sper = 0;
-  // optional element range of each selected line s = L % nsel: elements
-  // range[2 s] <= i < range[2 s + 1] only (the others read as zero on input,
-  // are not stored on output)
+  // optional element ranges of each selected line s: elements
+  // range[4 s] <= i < range[4 s + 1] and range[4 s + 2] <= i < range[4 s + 3]
+  // only (the others read as zero on input, are not stored on output)
   const int32_t *range = nullptr;
   // fin > 0: fields innermost in the pass numbering, L = l fin + f (the
   // fields of one line are consecutive pass lines): line l (through sel if

@@ -588,17 +588,25 @@ void setup_mesh_device(Plan *pl, MeshDev &md, hipStream_t s) {
       for (int64_t x = 0; x < h.grid[0]; ++x)
         if (yr[2 * x] > yr[2 * x + 1]) yr[2 * x] = yr[2 * x + 1] = 0;
       md.occ_yrange = upload(pl, yr.data(), yr.size(), s);
-      std::vector<int32_t> zr;  // occupied nodes are increasing, so lines come in order
+      // per occupied line {lo, g0, g1, hi}: its occupied nodes lie in
+      // [lo, hi) outside the longest unoccupied run [g0, g1) between them (a
+      // line through a closed surface crosses it twice); occupied nodes are
+      // increasing, so lines come in order
+      std::vector<int32_t> zr;
       for (int64_t i = 0; i < md.n_occ; ++i) {
         const int32_t line = occ[i] / h.grid[2], z = occ[i] % h.grid[2];
         if (zr.empty() || line != occ[i - 1] / h.grid[2]) {
-          zr.push_back(z);
-          zr.push_back(z + 1);
+          zr.insert(zr.end(), {z, z + 1, z + 1, z + 1});
         } else {
-          zr.back() = z + 1;
+          int32_t *r = &zr[zr.size() - 4];
+          if (z - r[3] > r[2] - r[1]) {  // a longer unoccupied run r[3] .. z - 1
+            r[1] = r[3];
+            r[2] = z;
+          }
+          r[3] = z + 1;
         }
       }
-      if (zr.empty()) zr.assign(2, 0);
+      if (zr.empty()) zr.assign(4, 0);
       md.occ_zrange = upload(pl, zr.data(), zr.size(), s);
       HIPCHECK(hipStreamSynchronize(s));  // host vectors go out of scope
     }

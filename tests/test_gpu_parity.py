@@ -375,10 +375,17 @@ def test_product_stages(name, prec):
         ys = np.flatnonzero(lines[i])
         if ys.size:
             ymask[i, ys[0]:ys[-1] + 1] = True
-    zmask = np.zeros((Nx, Ny, Nz), dtype=bool)  # occupied lines over their occupied z range
+    # occupied lines over their occupied z range, less the longest run of
+    # unoccupied nodes inside it (the first on ties): the nodes the inverse z
+    # pass writes, every occupied node among them
+    zmask = np.zeros((Nx, Ny, Nz), dtype=bool)
     for i, j in zip(*np.nonzero(lines)):
         zs = np.flatnonzero(occ[i, j])
         zmask[i, j, zs[0]:zs[-1] + 1] = True
+        if zs.size > 1:
+            k = int(np.argmax(np.diff(zs)))
+            zmask[i, j, zs[k] + 1:zs[k + 1]] = False
+    assert zmask[occ].all()
     R = x.shape[0]
     for stage in range(1, 7):
         _log(f"[product_stages {name} {prec}] stage {stage}")
