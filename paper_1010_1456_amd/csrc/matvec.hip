@@ -23,7 +23,8 @@ namespace {
 // many entries, so that a wave's entries stay few), whose entries are contiguous:
 // the wave loads them epl * 64 at a time (coalesced; every lane has epl
 // independent gathers in flight), each lane forming its entries' four products
-// in LDS, and every lane then sums the slots of its own node (one right-hand
+// in LDS; then the 64 / npw lanes of each node sum every (64 / npw)-th of its
+// slots and combine their sums by exchanges within the group (one right-hand
 // side per blockIdx.y). Entries per lane
 // per chunk: 2 (measured on the sphere over the occupied nodes: 1 or 4 is
 // slower for float, 1 for double by 30%)
@@ -51,8 +52,11 @@ __global__ void __launch_bounds__(256)
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t v0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + w) * npw;
   if (v0 >= V0) return;  // whole wave exits; no block-wide barrier is used
-  const int64_t v = v0 + lane;
-  const bool ok = lane < npw && v < V0;
+  // G = 64 / npw lanes per node (npw divides 64, checked by the launcher):
+  // lane = node * G + sub
+  const int G = 64 / npw, sub = lane & (G - 1);
+  const int64_t v = v0 + lane / G;
+  const bool ok = v < V0;
   const int64_t vend = (v0 + npw < V0) ? v0 + npw : V0;
   const int e0 = ok ? node_ptr[v] : 0, e1 = ok ? node_ptr[v + 1] : 0;
   const int w0 = node_ptr[v0], w1 = node_ptr[vend];
@@ -87,7 +91,7 @@ __global__ void __launch_bounds__(256)
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const int lo = (e0 > c0 ? e0 : c0) - c0, hi = (e1 < c0 + C ? e1 : c0 + C) - c0;
-      for (int k = lo; k < hi; ++k) {
+      for (int k = lo + sub; k < hi; k += G) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const cx<T> p = slot[w][k][q];
@@ -99,7 +103,13 @@ __global__ void __launch_bounds__(256)
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    if (ok) {
+    for (int off = 1; off < G; off <<= 1)  // the group's partial sums, fixed order
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        a[q][0] += __shfl_xor(a[q][0], off, 64);
+        a[q][1] += __shfl_xor(a[q][1], off, 64);
+      }
+    if (ok && sub == 0) {
       const int64_t node = occ ? (int64_t)occ[v] : v;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -434,6 +444,8 @@ void far_stages(Plan *pl, MeshDev &md, int nrhs, const cx<TX> *x, int64_t ldx, i
   const int64_t V0 = (int64_t)Nx * Ny * Nz;
   const int blk = kGridBlock<T>;
   const int npw = md.gather_npw[prec];
+  if (npw < 1 || npw > 64 || 64 % npw != 0)
+    throw Error(AIM_ERR_ARG, "projection gather: nodes per wave must divide 64");
   if (md.planar_z >= 0 && !full3d) {
     // every source on the plane z = planar_z, and only that plane weighted by
     // the interpolation: the plane alone, g0 = [F][Nx][Ny], 2-D propagation
